@@ -1,0 +1,343 @@
+"""FP64 CPU oracle for the Monte Carlo collision term (arXiv:1912.04457).
+
+TEST INFRASTRUCTURE ONLY.  This module and the C library it drives are the
+plain, slow reference the GPU path is checked against.  Only ``tests/``,
+``__graft_entry__.smoke()`` and the CPU-baseline leg of ``bench.py`` may import
+it.  It shares no code with the GPU library and imports nothing from it.
+
+Arrays follow the layout of the C oracle: ``f`` and ``A`` are float64 arrays of
+shape ``(7, cells, nodes)`` (species u, d, s, ubar, dbar, sbar, g), ``mass2`` is
+``(7, cells)``.
+
+The time step (``step``) composes the C primitives the way Sec. III of the
+paper states it: thermal masses (Eq. mg, Eq. mq, with E = |p| on the first
+step and the lagged masses afterwards), the collision term, the drift in flux
+form (Eq. left handside), and a forward-Euler update.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle_qgbe.so")
+SRC = os.path.join(HERE, "qgbe_oracle.c")
+
+HBARC = 0.1973269804  # GeV fm
+SPECIES = ("u", "d", "s", "ubar", "dbar", "sbar", "g")
+GLUON = 6
+DEGENERACY = np.array([6.0] * 6 + [16.0])  # N_q = 2*3, N_g = 2*8
+
+REF_B_ONE, REF_NO_BOXCUT, REF_MASSLESS, REF_ANALYTIC_F = 1, 2, 4, 8
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc (plain -O2, no FMA contraction)."""
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < max(
+        os.path.getmtime(SRC), os.path.getmtime(os.path.join(HERE, "qgbe_oracle.h"))
+    ):
+        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+               "-Wall", "-o", LIB_PATH + ".tmp", SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(LIB_PATH + ".tmp", LIB_PATH)
+    return LIB_PATH
+
+
+class _Grid(C.Structure):
+    _fields_ = [("n_x", C.c_int32 * 3), ("n_p", C.c_int32 * 3),
+                ("x_half", C.c_double * 3), ("p_half", C.c_double * 3),
+                ("species_mask", C.c_uint32), ("row_mask", C.c_uint32),
+                ("alpha_s", C.c_double)]
+
+
+class _Channel(C.Structure):
+    _fields_ = [("row", C.c_int32), ("sp", C.c_int32 * 4), ("code", C.c_int32),
+                ("w", C.c_double), ("sigma", C.c_double)]
+
+
+class _Eq(C.Structure):
+    _fields_ = [("T", C.c_double), ("mu", C.c_double * 7)]
+
+
+class _Point(C.Structure):
+    _fields_ = [("valid", C.c_int32), ("k", (C.c_double * 4) * 4),
+                ("s", C.c_double), ("t", C.c_double), ("u", C.c_double),
+                ("pstar", C.c_double), ("msq", C.c_double), ("f", C.c_double * 4),
+                ("B", C.c_double), ("GL", C.c_double), ("g", C.c_double),
+                ("gscale", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        d, i32, u32, u64, p = C.c_double, C.c_int32, C.c_uint32, C.c_uint64, C.c_void_p
+        _lib.ref_philox4x32_10.argtypes = [p, p, p]
+        _lib.ref_msq.restype = d
+        _lib.ref_msq.argtypes = [i32, d, d, d, d, d]
+        _lib.ref_channels.restype = i32
+        _lib.ref_channels.argtypes = [p, p, i32]
+        _lib.ref_masses.restype = i32
+        _lib.ref_masses.argtypes = [p, p, p, p]
+        _lib.ref_eval_cm.restype = i32
+        _lib.ref_eval_cm.argtypes = [p, p, p, p, i32, p, i32, p, d, d, i32, p, p]
+        _lib.ref_collision.restype = i32
+        _lib.ref_collision.argtypes = [p, p, p, u64, u32, i32, i32, i32, i32, p, p, p, p, i32]
+        _lib.ref_collision_learned.restype = i32
+        _lib.ref_collision_learned.argtypes = [p, p, p, u64, u32, i32, i32, p, p, p, i32,
+                                               p, p, p, i32]
+        _lib.ref_collision_points.restype = i32
+        _lib.ref_collision_points.argtypes = [p, p, p, C.c_int64, p, p, i32, i32, p, i32]
+        _lib.ref_drift.restype = i32
+        _lib.ref_drift.argtypes = [p, p, p, i32, p]
+        _lib.ref_observables.restype = i32
+        _lib.ref_observables.argtypes = [p, p, p, p, p, p]
+    return _lib
+
+
+def _ptr(a: np.ndarray | None):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+@dataclass
+class Grid:
+    """Phase-space grid and physics switches (cell-centred momentum nodes)."""
+    n_x: tuple = (1, 1, 1)
+    n_p: tuple = (10, 10, 10)
+    x_half: tuple = (3.0, 3.0, 3.0)
+    p_half: tuple = (2.0, 2.0, 2.0)
+    species_mask: int = 1 << GLUON
+    row_mask: int = 0x7F
+    alpha_s: float = 0.3
+
+    @property
+    def cells(self) -> int:
+        return int(np.prod(self.n_x))
+
+    @property
+    def nodes(self) -> int:
+        return int(np.prod(self.n_p))
+
+    def c(self) -> _Grid:
+        g = _Grid()
+        g.n_x[:] = list(self.n_x)
+        g.n_p[:] = list(self.n_p)
+        g.x_half[:] = [float(v) for v in self.x_half]
+        g.p_half[:] = [float(v) for v in self.p_half]
+        g.species_mask = self.species_mask
+        g.row_mask = self.row_mask
+        g.alpha_s = self.alpha_s
+        return g
+
+    def momenta(self) -> np.ndarray:
+        """Node momenta, shape (nodes, 3), pz fastest."""
+        axes = [-ph + (np.arange(n) + 0.5) * 2 * ph / n for n, ph in zip(self.n_p, self.p_half)]
+        P = np.stack(np.meshgrid(*axes, indexing="ij"), axis=-1)
+        return P.reshape(-1, 3)
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = np.asarray(ctr, dtype=np.uint32).copy()
+    k = np.asarray(key, dtype=np.uint32).copy()
+    out = np.zeros(4, dtype=np.uint32)
+    lib().ref_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def msq(row: int, s: float, t: float, u: float, mg2: float, alpha_s: float) -> float:
+    return lib().ref_msq(row, s, t, u, mg2, alpha_s)
+
+
+def channels(grid: Grid) -> list[dict]:
+    buf = (_Channel * 128)()
+    g = grid.c()
+    n = lib().ref_channels(C.byref(g), buf, 128)
+    if n < 0:
+        raise RuntimeError("channel table overflow")
+    return [dict(row=buf[i].row, sp=tuple(buf[i].sp), code=buf[i].code, w=buf[i].w,
+                 sigma=buf[i].sigma) for i in range(n)]
+
+
+def _field(grid: Grid, a) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.shape != (7, grid.cells, grid.nodes):
+        raise ValueError(f"expected f of shape {(7, grid.cells, grid.nodes)}, got {a.shape}")
+    return a
+
+
+def _mass(grid: Grid, m) -> np.ndarray:
+    m = np.ascontiguousarray(m, dtype=np.float64)
+    if m.shape != (7, grid.cells):
+        raise ValueError(f"expected mass2 of shape {(7, grid.cells)}, got {m.shape}")
+    return m
+
+
+def masses(grid: Grid, f, mass2_lag=None) -> np.ndarray:
+    """Eq. mg / Eq. mq; ``mass2_lag=None`` uses E = |p| (first time step)."""
+    f = _field(grid, f)
+    lag = None if mass2_lag is None else _mass(grid, mass2_lag)
+    out = np.zeros((7, grid.cells))
+    g = grid.c()
+    if lib().ref_masses(C.byref(g), _ptr(f), _ptr(lag), _ptr(out)) != 0:
+        raise ValueError("bad grid")
+    return out
+
+
+def constant_masses(grid: Grid, m2_by_species) -> np.ndarray:
+    m = np.asarray(m2_by_species, dtype=np.float64).reshape(7, 1)
+    return np.repeat(m, grid.cells, axis=1)
+
+
+def eval_cm(grid: Grid, chan: dict, f, mass2, cell: int, p1, p2, cos_th: float, phi: float,
+            flags: int = 0, eq: dict | None = None, p1_lin: int = -1) -> dict:
+    """Evaluate the CM-angle parameterisation at one configuration."""
+    f = _field(grid, f)
+    mass2 = _mass(grid, mass2)
+    ch = _Channel(chan["row"], (C.c_int32 * 4)(*chan["sp"]), chan["code"], chan["w"], chan["sigma"])
+    e = _make_eq(eq)
+    pt = _Point()
+    g = grid.c()
+    a1 = np.asarray(p1, dtype=np.float64)
+    a2 = np.asarray(p2, dtype=np.float64)
+    lib().ref_eval_cm(C.byref(g), C.byref(ch), _ptr(f), _ptr(mass2), cell, _ptr(a1), p1_lin,
+                      _ptr(a2), cos_th, phi, flags, None if e is None else C.byref(e), C.byref(pt))
+    return dict(valid=bool(pt.valid), k=np.array([[pt.k[i][j] for j in range(4)] for i in range(4)]),
+                s=pt.s, t=pt.t, u=pt.u, pstar=pt.pstar, msq=pt.msq, f=np.array(pt.f[:]),
+                B=pt.B, GL=pt.GL, g=pt.g, gscale=pt.gscale)
+
+
+def _make_eq(eq):
+    if eq is None:
+        return None
+    e = _Eq()
+    e.T = eq["T"]
+    e.mu[:] = list(eq.get("mu", [0.0] * 7))
+    return e
+
+
+def collision(grid: Grid, f, mass2, seed: int, step: int, n_samples: int, *, estimator: str = "cm",
+              symmetric: bool = True, flags: int = 0, eq: dict | None = None,
+              want_scale: bool = True, want_items: bool = False, threads: int = 0):
+    """Monte Carlo collision term A = N_Y C_Y with the uniform sampler.
+
+    Returns (A, S, items): S is the gain+loss scale (or None), items the
+    per-(cell, channel, p1) sums of the direct part (or None).
+    """
+    f = _field(grid, f)
+    mass2 = _mass(grid, mass2)
+    A = np.zeros_like(f)
+    S = np.zeros_like(f) if want_scale else None
+    nch = len(channels(grid))
+    items = np.zeros((grid.cells, nch, grid.nodes)) if want_items else None
+    e = _make_eq(eq)
+    g = grid.c()
+    est = {"cm": 0, "root": 1}[estimator]
+    r = lib().ref_collision(C.byref(g), _ptr(f), _ptr(mass2), seed, step, n_samples, est,
+                            int(symmetric), flags, None if e is None else C.byref(e),
+                            _ptr(A), _ptr(S), _ptr(items), threads)
+    if r < 0:
+        raise ValueError("oracle rejected the arguments")
+    return A, S, items
+
+
+def collision_learned(grid: Grid, f, mass2, seed: int, step: int, n_samples: int, thr, mu, sigma, *,
+                      table_per_cell: bool = False, want_scale: bool = True,
+                      want_items: bool = False, threads: int = 0):
+    """Collision term with the mixture proposal given as a table (see header)."""
+    f = _field(grid, f)
+    mass2 = _mass(grid, mass2)
+    thr = np.ascontiguousarray(thr, dtype=np.uint32)
+    mu = np.ascontiguousarray(mu, dtype=np.float32)
+    sigma = np.ascontiguousarray(sigma, dtype=np.float32)
+    K = thr.shape[-1]
+    nch = len(channels(grid))
+    rows = (grid.cells if table_per_cell else 1) * nch * grid.nodes
+    if thr.size != rows * K or mu.size != rows * K * 5 or sigma.size != rows * K * 5:
+        raise ValueError("table shape does not match the grid")
+    A = np.zeros_like(f)
+    S = np.zeros_like(f) if want_scale else None
+    items = np.zeros((grid.cells, nch, grid.nodes)) if want_items else None
+    g = grid.c()
+    r = lib().ref_collision_learned(C.byref(g), _ptr(f), _ptr(mass2), seed, step, n_samples, K,
+                                    _ptr(thr), _ptr(mu), _ptr(sigma), int(table_per_cell),
+                                    _ptr(A), _ptr(S), _ptr(items), threads)
+    if r < 0:
+        raise ValueError("oracle rejected the arguments")
+    return A, S, items
+
+
+def collision_points(grid: Grid, f, mass2, pts, wts, *, symmetric: bool = True,
+                     flags: int = 0, threads: int = 0) -> np.ndarray:
+    """The collision operator by quadrature over (p2, cos theta, phi) nodes."""
+    f = _field(grid, f)
+    mass2 = _mass(grid, mass2)
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 5)
+    wts = np.ascontiguousarray(wts, dtype=np.float64).reshape(-1)
+    if pts.shape[0] != wts.shape[0]:
+        raise ValueError("points and weights differ in length")
+    A = np.zeros_like(f)
+    g = grid.c()
+    if lib().ref_collision_points(C.byref(g), _ptr(f), _ptr(mass2), pts.shape[0], _ptr(pts),
+                                  _ptr(wts), int(symmetric), flags, _ptr(A), threads) < 0:
+        raise ValueError("oracle rejected the arguments")
+    return A
+
+
+def drift(grid: Grid, f, mass2, scheme: str = "upwind") -> np.ndarray:
+    f = _field(grid, f)
+    mass2 = _mass(grid, mass2)
+    D = np.zeros_like(f)
+    g = grid.c()
+    if lib().ref_drift(C.byref(g), _ptr(f), _ptr(mass2), {"upwind": 0, "central": 1}[scheme], _ptr(D)):
+        raise ValueError("bad grid")
+    return D
+
+
+def observables(grid: Grid, f, mass2) -> dict:
+    f = _field(grid, f)
+    mass2 = _mass(grid, mass2)
+    N = np.zeros(7)
+    E = np.zeros(7)
+    P = np.zeros((7, 3))
+    g = grid.c()
+    lib().ref_observables(C.byref(g), _ptr(f), _ptr(mass2), _ptr(N), _ptr(E), _ptr(P))
+    return dict(N=N, E=E, P=P, N_total=float(N.sum()), E_total=float(E.sum()))
+
+
+@dataclass
+class State:
+    """Evolving state of the oracle's time stepper."""
+    f: np.ndarray
+    step: int = 0
+    mass2_lag: np.ndarray | None = None
+    history: list = field(default_factory=list)
+
+
+def step(grid: Grid, state: State, dt_fm: float, n_samples: int, seed: int, *,
+         scheme: str = "upwind", symmetric: bool = True, const_mass2=None,
+         threads: int = 0) -> dict:
+    """One forward-Euler step f <- f + dt (A/(N_Y hbar c) - D[f]) (Sec. III)."""
+    if const_mass2 is not None:
+        m2 = constant_masses(grid, const_mass2)
+    else:
+        m2 = masses(grid, state.f, state.mass2_lag)
+    A, _, _ = collision(grid, state.f, m2, seed, state.step, n_samples, symmetric=symmetric,
+                        want_scale=False, threads=threads)
+    D = drift(grid, state.f, m2, scheme)
+    evolve = np.array([(grid.species_mask >> sp) & 1 for sp in range(7)], dtype=bool)
+    upd = dt_fm * (A / (DEGENERACY[:, None, None] * HBARC) - D)
+    upd[~evolve] = 0.0
+    state.f = state.f + upd
+    state.mass2_lag = m2
+    state.step += 1
+    obs = observables(grid, state.f, m2)
+    obs["mass2"] = m2
+    state.history.append(obs)
+    return obs

@@ -1,0 +1,218 @@
+/*
+ * qgbe.h -- C ABI of libqgbe: Monte Carlo 2->2 collision term of the
+ * relativistic Boltzmann equation for quarks and gluons, with its explicit
+ * drift and time step, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Zhang, Wu, Pu, Qin, Wang, "Towards a full solution of relativistic
+ * Boltzmann equation for quark-gluon matter on GPUs" (arXiv:1912.04457).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Species      0..6 = u, d, s, ubar, dbar, sbar, g.  Degeneracies N_q = 6,
+ *              N_g = 16 (Eq. C_quark, Eq. C_gluon).
+ * Grid         cell-centred.  Momentum node i of an axis sits at
+ *              -p_half + (i + 1/2) * 2 p_half / n_p (GeV); spatial cells
+ *              likewise with x_half (fm).  Boundaries are periodic in x and p
+ *              for the drift (Sec. III).
+ * Layout       distributions and collision terms are float64
+ *              [species][cell][node], cell = (ix*ny + iy)*nz + iz,
+ *              node = (ipx*npy + ipy)*npz + ipz (pz fastest).
+ * A            the collision output A_Y(x,q) = N_Y C_Y(x,q) in GeV, i.e. the
+ *              left-hand side of Eq. C_quark / Eq. C_gluon.
+ * Channels     one per (reaction of Table I, species placed first), ordered by
+ *              code = ((s1*7+s2)*7+s3)*7+s4 ascending; 70 for all 7 species.
+ * Random draws Philox4x32-10 with key (seed_lo, seed_hi + step) and counter
+ *              (sample, node, cell, code<<8 | block): every sample is a pure
+ *              function of (seed, step, cell, channel, node, sample).
+ * Pointers     "on_device" = 1: a device pointer on the context's device
+ *              (e.g. a torch tensor's data_ptr), used on the context's stream;
+ *              0: host memory.  The caller owns every buffer it passes and keeps
+ *              device buffers alive until the stream has finished with them.
+ *              The library owns the context and the device workspace it
+ *              allocates in qgbe_init_grid (reported by qgbe_workspace_bytes).
+ * Errors       every entry point returns a qgbe_status; nothing is thrown
+ *              across the ABI.  Argument errors are reported before any device
+ *              work.  qgbe_last_error() gives a message for the calling thread.
+ * Streams      device work is enqueued on the context's stream.  Calls that
+ *              return host data (stats, host outputs) synchronise that stream.
+ */
+#ifndef QGBE_H
+#define QGBE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qgbe_ctx qgbe_ctx;
+
+typedef enum {
+  QGBE_OK = 0,
+  QGBE_EINVAL = -1,       /* bad argument (sizes, masks, null pointers)       */
+  QGBE_ENOMEM = -2,       /* device allocation failed                          */
+  QGBE_EDEVICE = -3,      /* a HIP call failed                                 */
+  QGBE_ESTATE = -4,       /* call not valid in the context's current state     */
+  QGBE_ENUMERIC = -5,     /* NaN/Inf found in the evolved distribution         */
+  QGBE_EUNSUPPORTED = -6  /* configuration not supported by this build         */
+} qgbe_status;
+
+enum { QGBE_FP64 = 0, QGBE_FP32 = 1 };                 /* integrand precision   */
+enum { QGBE_SAMPLER_UNIFORM = 0, QGBE_SAMPLER_LEARNED = 1 };
+enum { QGBE_DRIFT_UPWIND = 0, QGBE_DRIFT_CENTRAL = 1 };
+enum { QGBE_MASS_DYNAMIC = 0, QGBE_MASS_CONSTANT = 1 };
+
+/* stats flags */
+enum { QGBE_FLAG_NEGATIVE_F = 1, QGBE_FLAG_PAULI = 2, QGBE_FLAG_NONFINITE = 4 };
+
+typedef struct {
+  int32_t n_x[3];          /* spatial cells per axis, >= 1                    */
+  int32_t n_p[3];          /* momentum nodes per axis, >= 2                   */
+  double x_half[3];        /* spatial box half-widths, fm, > 0                */
+  double p_half[3];        /* momentum box half-widths, GeV, > 0              */
+  uint32_t species_mask;   /* bit Y: species Y evolves; a reaction is included
+                              when all four of its species evolve             */
+  uint32_t row_mask;       /* bit r-1: Table I row r enabled                  */
+  double alpha_s;          /* strong coupling, g^2 = 4 pi alpha_s             */
+  int32_t precision;       /* QGBE_FP64 or QGBE_FP32 (FP32 integrand and f
+                              interpolation, FP64 sample geometry and FP64
+                              accumulation)                                   */
+  int32_t symmetric;       /* 1: symmetric sampling (Sec. III B), 0: direct  */
+  int32_t drift;           /* QGBE_DRIFT_UPWIND or QGBE_DRIFT_CENTRAL         */
+  int32_t mass_mode;       /* QGBE_MASS_DYNAMIC (Eq. mg, Eq. mq) or CONSTANT  */
+  double const_mass2[7];   /* GeV^2 per species, used when mass_mode=CONSTANT */
+  uint64_t seed;           /* Philox seed                                     */
+  int32_t device;          /* HIP device ordinal                              */
+  void* stream;            /* hipStream_t; NULL = the default stream          */
+} qgbe_grid_desc;
+
+typedef struct {
+  double N_total;          /* Eq. particle numbers summed over species        */
+  double N[7];
+  double E_total;          /* T^00 of Eq. energy momentum tensor, integrated   */
+  double E[7];
+  double P[3];             /* total momentum                                   */
+  double mass2_avg[7];     /* cell-averaged thermal masses squared, GeV^2      */
+  double min_f;            /* minimum of f over evolved species                */
+  double max_fermion_f;    /* maximum of quark/antiquark f                     */
+  double n_evals;          /* integrand evaluations in the collision term     */
+  double t_collide_ms;     /* device time of the collision kernels             */
+  double t_step_ms;        /* device time of the whole step                    */
+  uint32_t flags;          /* QGBE_FLAG_*                                      */
+  uint32_t step;           /* step index the stats belong to                   */
+  double n_accepted;       /* evaluations above threshold and inside the box  */
+} qgbe_stats;
+
+/* Optional outputs of the collision term (all may be NULL). */
+typedef struct {
+  double* scale;           /* [7][cells][nodes] sum of |deposit| of the
+                              gain+loss magnitude, for error normalisation     */
+  double* item_sums;       /* [cells][channels][nodes] sum of the sample values
+                              of each work item (its direct part)              */
+  int32_t on_device;       /* where scale and item_sums live                   */
+} qgbe_collide_extras;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context: validates the descriptor, builds the channel table of
+ * Eq. C_quark / Eq. C_gluon, allocates the device workspace (f in FP64 and its
+ * FP32 shadow, masses, accumulators) and zeroes f.  *out is NULL on failure. */
+qgbe_status qgbe_init_grid(const qgbe_grid_desc* desc, qgbe_ctx** out);
+
+/* Release the context and its workspace (waits for its stream). NULL is fine. */
+void qgbe_destroy(qgbe_ctx* ctx);
+
+/* Message describing the last failure on the calling thread ("" if none).
+ * Valid until the next qgbe_* call on this thread. */
+const char* qgbe_last_error(void);
+
+/* Bytes of device memory the context owns. */
+size_t qgbe_workspace_bytes(const qgbe_ctx* ctx);
+
+/* ---- state -------------------------------------------------------------- */
+
+/* Copy f of one species ([cells][nodes], float64) into the context (species
+ * in 0..6), or all seven species at once with species = -1 ([7][cells][nodes]).
+ * Resets the lagged masses, so the next mass evaluation uses E = |p|
+ * (Sec. II, after Eq. mq). */
+qgbe_status qgbe_set_distribution(qgbe_ctx* ctx, int32_t species, const double* f,
+                                  int32_t on_device);
+
+/* Copy f out (same shapes as qgbe_set_distribution). */
+qgbe_status qgbe_get_distribution(qgbe_ctx* ctx, int32_t species, double* f,
+                                  int32_t on_device);
+
+/* Thermal masses squared [7][cells] (host) used by the last collision term or
+ * step.  Eq. mg / Eq. mq as midpoint sums over the momentum grid. */
+qgbe_status qgbe_get_masses(qgbe_ctx* ctx, double* mass2);
+
+/* Step index used as the second Philox key word; advanced by qgbe_step. */
+qgbe_status qgbe_set_step_index(qgbe_ctx* ctx, uint32_t step);
+qgbe_status qgbe_get_step_index(const qgbe_ctx* ctx, uint32_t* step);
+
+/* ---- the hot path ------------------------------------------------------- */
+
+/* The Monte Carlo collision term A = N_Y C_Y for every cell, species and node
+ * (Eq. C_a_b summed as in Eq. C_quark / Eq. C_gluon).  Thermal masses are
+ * evaluated first from the current f (lagged energies if a step has run).
+ * n_samples samples per (cell, channel, node); sampler QGBE_SAMPLER_UNIFORM
+ * draws p2 uniformly in the momentum box and the two CM angles uniformly
+ * (Eq. MC C_gg with the CM-angle parameterisation), QGBE_SAMPLER_LEARNED
+ * draws from the proposal table (qgbe_set_proposal_table).
+ * Symmetric sampling (Eq. small c relation) adds each sample's value at the
+ * observed node and at the trilinear stencils of the other three momenta with
+ * signs (+,+,-,-), so sum_{Y,q} A = 0 per cell exactly.
+ * A_out: [7][cells][nodes] float64, overwritten.  st may be NULL. */
+qgbe_status qgbe_collision_term(qgbe_ctx* ctx, int32_t n_samples, int32_t sampler,
+                                double* A_out, int32_t on_device, qgbe_stats* st);
+
+/* Same with optional diagnostic outputs (extras may be NULL). */
+qgbe_status qgbe_collision_term_ex(qgbe_ctx* ctx, int32_t n_samples, int32_t sampler,
+                                   double* A_out, int32_t on_device,
+                                   const qgbe_collide_extras* extras, qgbe_stats* st);
+
+/* n_steps forward-Euler steps (Sec. III):
+ *   masses -> collision term A -> drift D[f] of Eq. left handside (upwind or
+ *   the central differences of Eq. descrete left hand, periodic) ->
+ *   f += dt (A / (N_Y hbar c) - D[f]) -> observables.
+ * dt_fm in fm/c, hbar c = 0.1973269804 GeV fm.  Non-evolving species are
+ * frozen.  per_step: n_steps entries or NULL.  Returns QGBE_ENUMERIC (after
+ * finishing the step) if f became non-finite. */
+qgbe_status qgbe_step(qgbe_ctx* ctx, double dt_fm, int32_t n_samples, int32_t sampler,
+                      int32_t n_steps, qgbe_stats* per_step);
+
+/* Observables of the current f with the current masses (Eq. particle numbers,
+ * Eq. energy momentum tensor), FP64. */
+qgbe_status qgbe_observables(qgbe_ctx* ctx, qgbe_stats* st);
+
+/* ---- proposal table for the learned sampler ------------------------------ */
+
+/* Install a mixture-of-logistic-normals proposal over the five unit-cube
+ * variables (p2 in the box, cos theta*, phi*), one row per (channel, node):
+ *   thr   [rows][K] uint32: thr[0] = defensive-uniform share alpha * 2^32;
+ *         component k is drawn when thr[k] <= x < thr[k+1] (thr[K] = 2^32)
+ *   mu    [rows][K][5] float32 location in logit space
+ *   sigma [rows][K][5] float32 scale in logit space (> 0)
+ * rows = channels * nodes.  K in 1..16.  Copied into the workspace. */
+qgbe_status qgbe_set_proposal_table(qgbe_ctx* ctx, int32_t K, const uint32_t* thr,
+                                    const float* mu, const float* sigma, int32_t on_device);
+
+/* ---- host-only helpers (no device needed) ------------------------------- */
+
+/* The channel table the library builds for the masks: rows [n][5] =
+ * (Table I row, s1, s2, s3, s4) and weights [n][2] = (w, sigma) where w is the
+ * per-position symmetric weight and sigma the coefficient in Eq. C_quark /
+ * Eq. C_gluon.  Returns the count, or a negative qgbe_status if max is too
+ * small.  Either output may be NULL. */
+int32_t qgbe_channel_table(uint32_t species_mask, uint32_t row_mask, int32_t* rows,
+                           double* weights, int32_t max);
+
+/* Philox4x32-10 block (Salmon et al., SC'11) as the device computes it; host
+ * implementation for checks. */
+void qgbe_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QGBE_H */

@@ -93,6 +93,8 @@ def lib():
         _lib.ref_collision_learned.restype = i32
         _lib.ref_collision_learned.argtypes = [p, p, p, u64, u32, i32, i32, p, p, p, i32,
                                                p, p, p, i32]
+        _lib.ref_item_sums.restype = i32
+        _lib.ref_item_sums.argtypes = [p, p, p, u64, u32, i32, i32, C.c_int64, p, p, i32]
         _lib.ref_collision_points.restype = i32
         _lib.ref_collision_points.argtypes = [p, p, p, C.c_int64, p, p, i32, i32, p, i32]
         _lib.ref_drift.restype = i32
@@ -271,6 +273,20 @@ def collision_learned(grid: Grid, f, mass2, seed: int, step: int, n_samples: int
     if r < 0:
         raise ValueError("oracle rejected the arguments")
     return A, S, items
+
+
+def item_sums(grid: Grid, f, mass2, seed: int, step: int, n_samples: int, items, *,
+              symmetric: bool = True, threads: int = 0) -> np.ndarray:
+    """Sum of the sample values of each selected (cell, channel, node) item."""
+    f = _field(grid, f)
+    mass2 = _mass(grid, mass2)
+    items = np.ascontiguousarray(items, dtype=np.int64).reshape(-1, 3)
+    out = np.zeros(len(items))
+    g = grid.c()
+    if lib().ref_item_sums(C.byref(g), _ptr(f), _ptr(mass2), seed, step, n_samples, int(symmetric),
+                           len(items), _ptr(items), _ptr(out), threads) < 0:
+        raise ValueError("oracle rejected the arguments")
+    return out
 
 
 def collision_points(grid: Grid, f, mass2, pts, wts, *, symmetric: bool = True,

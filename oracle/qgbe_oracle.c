@@ -181,6 +181,11 @@ int32_t ref_channels(const ref_grid* g, ref_channel* out, int32_t max) {
       ch->sigma = (double)nX * kappa / (S_in * S_out);
     }
   }
+  /* canonical order: ascending channel code */
+  for (int i = 1; i < n; ++i)
+    for (int j = i; j > 0 && out[j - 1].code > out[j].code; --j) {
+      ref_channel tmp = out[j - 1]; out[j - 1] = out[j]; out[j] = tmp;
+    }
   return n;
 }
 
@@ -324,6 +329,9 @@ int32_t ref_eval_cm(const ref_grid* g, const ref_channel* ch, const double* f,
 
   double k1[4] = {sqrt(norm2(p1) + m2[0]), p1[0], p1[1], p1[2]};
   double k2[4] = {sqrt(norm2(p2) + m2[1]), p2[0], p2[1], p2[2]};
+  /* the 1/(2E) measure of Eq. C_a_b is singular at a massless p = 0; that
+     single point carries no weight (as in the thermal-mass sums) */
+  if (!(k1[0] > 0.0) || !(k2[0] > 0.0)) return 0;
   double P[4];
   for (int a = 0; a < 4; ++a) P[a] = k1[a] + k2[a];
   const double s = mink2(P);
@@ -401,6 +409,7 @@ static void deposit_sample(const ref_grid* g, const ref_channel* ch, accum* acc,
                            double vs, double v_direct, double vs_direct) {
   const int64_t nc = n_cells(g), nn = n_nodes(g);
   const int64_t at1 = ((int64_t)ch->sp[0] * nc + cell) * nn + p1_lin;
+  if (!acc->A) return; /* item sums only */
   if (!symmetric) {
     acc->A[at1] += v_direct;
     if (acc->S) acc->S[at1] += fabs(vs_direct);
@@ -700,6 +709,37 @@ static int32_t run_all(const run_args* ra, item_kind kind, double* A_out, double
   }
   free(bufA);
   free(bufS);
+  return nch;
+}
+
+/* direct sums of selected work items (cell, channel ordinal, node), without
+   deposits; items[3*i .. 3*i+2] */
+int32_t ref_item_sums(const ref_grid* g, const double* f, const double* mass2, uint64_t seed,
+                      uint32_t step, int32_t n_samples, int32_t symmetric, int64_t n_sel,
+                      const int64_t* items, double* out, int32_t n_threads) {
+  if (check_grid(g) || n_samples <= 0) return -1;
+  ref_channel chans[128];
+  const int nch = ref_channels(g, chans, 128);
+  if (nch < 0) return -1;
+  const int64_t nc = n_cells(g), nn = n_nodes(g);
+  for (int64_t i = 0; i < n_sel; ++i)
+    if (items[3 * i] < 0 || items[3 * i] >= nc || items[3 * i + 1] < 0 || items[3 * i + 1] >= nch ||
+        items[3 * i + 2] < 0 || items[3 * i + 2] >= nn)
+      return -1;
+  int nt = 1;
+#ifdef _OPENMP
+  nt = n_threads > 0 ? n_threads : omp_get_max_threads();
+#else
+  (void)n_threads;
+#endif
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nt) schedule(dynamic)
+#endif
+  for (int64_t i = 0; i < n_sel; ++i) {
+    accum acc = {NULL, NULL};
+    run_item_uniform(g, &chans[items[3 * i + 1]], f, mass2, seed, step, n_samples, REF_EST_CM,
+                     symmetric, 0, NULL, items[3 * i], items[3 * i + 2], &acc, &out[i]);
+  }
   return nch;
 }
 

@@ -81,7 +81,8 @@ void ref_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
 /* |M|^2 of Table I (summed over all colours and helicities) */
 double ref_msq(int32_t row, double s, double t, double u, double mg2, double alpha_s);
 
-/* channel table for the species/row masks; returns the count (<= max) */
+/* channel table for the species/row masks, in ascending order of code;
+   returns the count (<= max) */
 int32_t ref_channels(const ref_grid* g, ref_channel* out, int32_t max);
 
 /* thermal masses, Eq. mg and Eq. mq; mass2_lag == NULL means E = |p| */
@@ -108,6 +109,12 @@ int32_t ref_collision(const ref_grid* g, const double* f, const double* mass2,
                       int32_t estimator, int32_t symmetric, int32_t flags,
                       const ref_equilibrium* eq, double* A_out, double* S_out,
                       double* item_sum, int32_t n_threads);
+
+/* direct sums (sum of sample values) of selected work items without any
+   deposits: items[3i..3i+2] = (cell, channel ordinal, node); out[n_sel] */
+int32_t ref_item_sums(const ref_grid* g, const double* f, const double* mass2, uint64_t seed,
+                      uint32_t step, int32_t n_samples, int32_t symmetric, int64_t n_sel,
+                      const int64_t* items, double* out, int32_t n_threads);
 
 /* the collision term with a mixture-of-logistic-normals proposal.
  *   K          mixture components

@@ -1,0 +1,34 @@
+// Launch interface of the collision kernels.
+#pragma once
+
+#include "qgbe_common.h"
+
+namespace qgbe {
+
+struct CollideArgs {
+  Grid G;
+  const Channel* chans;   // device channel table (all channels)
+  const int* group;       // channel indices processed by this launch
+  int n_group;
+  int n_channels;         // total channels (layout of items)
+  int n_chunks;           // workgroups per (cell, channel) (FP32 kernel)
+  int chunk_items;        // observed nodes per workgroup (FP32 kernel)
+  int lds_tiles;          // f tiles staged in LDS (FP32 kernel)
+  int lds_acc;            // FP64 deposit accumulators in LDS (FP32 kernel)
+  int n_samples;
+  int symmetric;
+  uint32_t key0, key1;    // Philox key
+  const double* f64;      // [7][cells][nodes]
+  const float* f32;       // FP32 shadow of f64
+  const double* mass2;    // [7][cells]
+  double* A;              // [7][cells][nodes], accumulated into
+  double* scale;          // optional, same shape
+  double* items;          // optional [cells][n_channels][nodes]
+  unsigned long long* n_accepted;  // samples above threshold and inside the box
+};
+
+hipError_t launch_collide_f64(const CollideArgs& a, hipStream_t stream);
+hipError_t launch_collide_f32(const CollideArgs& a, int nslot, hipStream_t stream);
+hipError_t set_collide_lds_limit(size_t bytes);
+
+}  // namespace qgbe

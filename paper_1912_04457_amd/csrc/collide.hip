@@ -1,0 +1,526 @@
+// Monte Carlo collision term (Eq. C_a_b, Eq. MC C_gg, Eq. small c relation).
+//
+// Work item = (cell, channel, observed node p1).  One wavefront owns one item
+// at a time, so everything that depends only on the item (p1, E1, f1, masses,
+// channel) is wave-uniform; the 64 lanes draw samples s = lane, lane+64, ...
+//
+// Per sample (CM-angle parameterisation of the 5-D integral):
+//   Philox4x32-10 block -> five 23-bit uniforms -> p2 in the box, cos theta*,
+//   phi* -> E2, s, |p*| -> k1 boosted to the CM frame gives the polar axis ->
+//   p3* on the sphere -> boost back, p4 = P - p3 -> box cut -> t, u ->
+//   |M|^2 (Table I) -> trilinear f at p2, p3, p4 -> bracket
+//   B = f3 f4 F1 F2 - f1 f2 F3 F4 -> value v.
+// Symmetric sampling adds +v at (X, p1), +v W(p2) at species 2, -v W(p3) at
+// species 3 and -v W(p4) at species 4 (W: trilinear stencil weights).
+//
+// Precision: the sample geometry (everything that decides the threshold,
+// the box cut and the branch of the CM frame) is FP64 in both modes, so both
+// precisions reject exactly the samples an FP64 evaluation rejects; on CDNA4
+// FP64 add/mul/FMA issue at the rate of unpacked FP32.  The integrand
+// (|M|^2, interpolation, bracket, value) is FP32 in QGBE_FP32 mode.  Direct
+// sums are FP64; in FP32 mode the deposits go to FP32 LDS accumulators per
+// workgroup and are flushed into the FP64 output.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "collide.h"
+
+namespace qgbe {
+namespace {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ double unif23(uint32_t v) { return ((double)v + 0.5) * (1.0 / 8388608.0); }
+
+// Table I |M|^2 in units of g^4, every t and u pole regulated by mu = m_g^2.
+// Group factors (SU(3), fundamental quarks): 8 dF^2 CF^2/dA = 16,
+// 16 dF CF (CF - CA/2) = -32/3, 8 dF CF^2 = 128/3, 8 dF CF CA = 96,
+// 16 dA CA^2 = 1152.
+template <typename R>
+__device__ __forceinline__ R matrix_element(int row, R s, R t, R u, R mu) {
+  const R rt = R(1) / (t - mu);
+  const R ru = R(1) / (u - mu);
+  const R rs = R(1) / s;
+  const R s2 = s * s, t2 = t * t, u2 = u * u;
+  switch (row) {
+    case 1: return R(16) * (s2 + u2) * rt * rt;
+    case 2: return R(16) * ((s2 + u2) * rt * rt + (s2 + t2) * ru * ru) - R(32.0 / 3.0) * s2 * rt * ru;
+    case 3: return R(16) * ((s2 + u2) * rt * rt + (u2 + t2) * rs * rs) - R(32.0 / 3.0) * u2 * rt * rs;
+    case 4: return R(16) * (t2 + u2) * rs * rs;
+    case 5: return R(128.0 / 3.0) * (u * rt + t * ru) - R(96) * (t2 + u2) * rs * rs;
+    case 6: return R(-128.0 / 3.0) * (u * rs + s * ru) + R(96) * (s2 + u2) * rt * rt;
+    default: return R(1152) * (R(3) - s * u * rt * rt - s * t * ru * ru - t * u * rs * rs);
+  }
+}
+
+// Trilinear stencil over the 8 surrounding cell centres, clamped at the box.
+template <typename R>
+struct Stencil {
+  int base;
+  R wx, wy, wz;
+};
+
+// The grid coordinate and its fraction are formed in FP64 so the weights carry
+// a relative (not an absolute 2^-24 * n) error when rounded to R.
+template <typename R>
+__device__ __forceinline__ R clamp_axis(double p, double ph, double inv_dp, int n, int& i0) {
+  double t = fma(p + ph, inv_dp, -0.5);
+  t = t < 0.0 ? 0.0 : t;
+  const double top = (double)(n - 1);
+  t = t > top ? top : t;
+  int i = (int)t;
+  i = i > n - 2 ? n - 2 : i;
+  i0 = i;
+  return (R)(t - (double)i);
+}
+
+template <typename R>
+__device__ __forceinline__ Stencil<R> make_stencil(const double p[3], const Grid& G) {
+  Stencil<R> st;
+  int ix, iy, iz;
+  st.wx = clamp_axis<R>(p[0], G.ph[0], G.inv_dp[0], G.np[0], ix);
+  st.wy = clamp_axis<R>(p[1], G.ph[1], G.inv_dp[1], G.np[1], iy);
+  st.wz = clamp_axis<R>(p[2], G.ph[2], G.inv_dp[2], G.np[2], iz);
+  st.base = ix * G.ox + iy * G.oy + iz;
+  return st;
+}
+
+template <typename R, typename T>
+__device__ __forceinline__ R interpolate(const T* __restrict__ tile, const Stencil<R>& st, int ox, int oy) {
+  const T* q = tile + st.base;
+  const R f000 = q[0], f001 = q[1], f010 = q[oy], f011 = q[oy + 1];
+  const R f100 = q[ox], f101 = q[ox + 1], f110 = q[ox + oy], f111 = q[ox + oy + 1];
+  const R a00 = f000 + st.wz * (f001 - f000);
+  const R a01 = f010 + st.wz * (f011 - f010);
+  const R a10 = f100 + st.wz * (f101 - f100);
+  const R a11 = f110 + st.wz * (f111 - f110);
+  const R b0 = a00 + st.wy * (a01 - a00);
+  const R b1 = a10 + st.wy * (a11 - a10);
+  return b0 + st.wx * (b1 - b0);
+}
+
+// Scatter v with the stencil weights (the transpose of interpolate): values
+// in precision R, accumulators of type T.
+template <typename R, typename T>
+__device__ __forceinline__ void deposit(T* acc, const Stencil<R>& st, R v, int ox, int oy) {
+  T* q = acc + st.base;
+  const R vx1 = v * st.wx, vx0 = v - vx1;
+  const R v01 = vx0 * st.wy, v00 = vx0 - v01;
+  const R v11 = vx1 * st.wy, v10 = vx1 - v11;
+  atomicAdd(q, (T)(v00 - v00 * st.wz));
+  atomicAdd(q + 1, (T)(v00 * st.wz));
+  atomicAdd(q + oy, (T)(v01 - v01 * st.wz));
+  atomicAdd(q + oy + 1, (T)(v01 * st.wz));
+  atomicAdd(q + ox, (T)(v10 - v10 * st.wz));
+  atomicAdd(q + ox + 1, (T)(v10 * st.wz));
+  atomicAdd(q + ox + oy, (T)(v11 - v11 * st.wz));
+  atomicAdd(q + ox + oy + 1, (T)(v11 * st.wz));
+}
+
+// Quantities of a work item, identical for all lanes of the wave.
+struct Item {
+  int cell, p1_lin;
+  double p1[3];
+  double E1;
+  double m2sq, m3sq, m4sq;
+  double thr;               // (m3 + m4)^2
+  double sum2, dif2;        // (m3 + m4)^2, (m3 - m4)^2
+  double mu;                // regulator m_g^2
+  double f1;
+  double coef;              // w V5 / N (symmetric) or sigma V5 / N (direct)
+};
+
+// The sampled configuration (FP64 geometry).
+struct Geo {
+  double p2[3], p3[3], p4[3];
+  double E2, s, t, u, rs, pstar;
+};
+
+// Sample geometry from the five uniforms; false if below threshold or outside the box.
+__device__ __forceinline__ bool geometry(const Item& it, const Grid& G, const double u[5], Geo& g) {
+  for (int a = 0; a < 3; ++a) g.p2[a] = fma(2.0 * G.ph[a], u[a], -G.ph[a]);
+  g.E2 = sqrt(g.p2[0] * g.p2[0] + g.p2[1] * g.p2[1] + g.p2[2] * g.p2[2] + it.m2sq);
+  const double E = it.E1 + g.E2;
+  const double P[3] = {it.p1[0] + g.p2[0], it.p1[1] + g.p2[1], it.p1[2] + g.p2[2]};
+  const double s = E * E - (P[0] * P[0] + P[1] * P[1] + P[2] * P[2]);
+  g.s = s;
+  if (!(s > it.thr)) return false;
+  const double rs = 1.0 / sqrt(s);
+  const double sq = s * rs;
+  g.rs = rs;
+  g.pstar = 0.5 * rs * sqrt((s - it.sum2) * (s - it.dif2));
+  // k1 in the CM frame: p1* = p1 + P ((P.p1)/(sqrt s (E + sqrt s)) - E1/sqrt s)
+  const double inv_E = 1.0 / (E + sq);
+  const double Pp1 = P[0] * it.p1[0] + P[1] * it.p1[1] + P[2] * it.p1[2];
+  const double c1 = (Pp1 * inv_E - it.E1) * rs;
+  double n[3] = {it.p1[0] + P[0] * c1, it.p1[1] + P[1] * c1, it.p1[2] + P[2] * c1};
+  const double rn = 1.0 / sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  n[0] *= rn; n[1] *= rn; n[2] *= rn;
+  // orthonormal completion of n (Duff et al., JCGT 6(1), 2017)
+  const double sgn = copysign(1.0, n[2]);
+  const double a = -1.0 / (sgn + n[2]);
+  const double b = n[0] * n[1] * a;
+  const double e1[3] = {1.0 + sgn * n[0] * n[0] * a, sgn * b, -sgn * n[0]};
+  const double e2[3] = {b, sgn + n[1] * n[1] * a, -n[1]};
+  const double cth = 2.0 * u[3] - 1.0;
+  const double sth = 2.0 * sqrt(u[3] * (1.0 - u[3]));
+  double sphi, cphi;
+  sincospi(2.0 * u[4], &sphi, &cphi);
+  const double sc = sth * cphi, ss = sth * sphi;
+  double p3s[3];
+  for (int k = 0; k < 3; ++k) p3s[k] = g.pstar * (sc * e1[k] + ss * e2[k] + cth * n[k]);
+  const double E3s = 0.5 * (s + it.m3sq - it.m4sq) * rs;
+  const double Pp3 = P[0] * p3s[0] + P[1] * p3s[1] + P[2] * p3s[2];
+  const double c3 = (Pp3 * inv_E + E3s) * rs;
+  for (int k = 0; k < 3; ++k) {
+    g.p3[k] = p3s[k] + P[k] * c3;
+    g.p4[k] = P[k] - g.p3[k];
+  }
+  const double E3 = (E * E3s + Pp3) * rs;
+  const double E4 = E - E3;
+  for (int k = 0; k < 3; ++k) {
+    if (!(fabs(g.p3[k]) <= G.ph[k]) || !(fabs(g.p4[k]) <= G.ph[k])) return false;
+  }
+  const double d13[3] = {it.p1[0] - g.p3[0], it.p1[1] - g.p3[1], it.p1[2] - g.p3[2]};
+  const double d14[3] = {it.p1[0] - g.p4[0], it.p1[1] - g.p4[1], it.p1[2] - g.p4[2]};
+  g.t = (it.E1 - E3) * (it.E1 - E3) - (d13[0] * d13[0] + d13[1] * d13[1] + d13[2] * d13[2]);
+  g.u = (it.E1 - E4) * (it.E1 - E4) - (d14[0] * d14[0] + d14[1] * d14[1] + d14[2] * d14[2]);
+  return true;
+}
+
+// Five 23-bit uniforms from one Philox block: the top 23 bits of each word,
+// and for the fifth the low 9 bits of words 0 and 1 and bits 4..8 of word 2.
+__device__ __forceinline__ void five_uniforms(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3, double u[5]) {
+  u[0] = unif23(x0 >> 9);
+  u[1] = unif23(x1 >> 9);
+  u[2] = unif23(x2 >> 9);
+  u[3] = unif23(x3 >> 9);
+  u[4] = unif23(((x0 & 0x1FFu) << 14) | ((x1 & 0x1FFu) << 5) | ((x2 & 0x1FFu) >> 4));
+}
+
+__device__ __forceinline__ int wave_count(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Set up the wave-uniform item constants.
+__device__ __forceinline__ void load_item(Item& it, const CollideArgs& A, const Channel& ch, int cell, int p1_lin) {
+  const Grid& G = A.G;
+  it.cell = cell;
+  it.p1_lin = p1_lin;
+  const int iz = p1_lin % G.np[2];
+  const int iy = (p1_lin / G.np[2]) % G.np[1];
+  const int ix = p1_lin / (G.np[2] * G.np[1]);
+  it.p1[0] = -G.ph[0] + (ix + 0.5) * G.dp[0];
+  it.p1[1] = -G.ph[1] + (iy + 0.5) * G.dp[1];
+  it.p1[2] = -G.ph[2] + (iz + 0.5) * G.dp[2];
+  const double m1sq = A.mass2[ch.sp[0] * G.cells + cell];
+  it.m2sq = A.mass2[ch.sp[1] * G.cells + cell];
+  it.m3sq = A.mass2[ch.sp[2] * G.cells + cell];
+  it.m4sq = A.mass2[ch.sp[3] * G.cells + cell];
+  it.mu = A.mass2[kGluon * G.cells + cell];
+  it.E1 = sqrt(it.p1[0] * it.p1[0] + it.p1[1] * it.p1[1] + it.p1[2] * it.p1[2] + m1sq);
+  const double m3 = sqrt(it.m3sq), m4 = sqrt(it.m4sq);
+  it.sum2 = (m3 + m4) * (m3 + m4);
+  it.dif2 = (m3 - m4) * (m3 - m4);
+  it.thr = it.sum2;
+  it.f1 = A.f64[((size_t)ch.sp[0] * G.cells + cell) * G.nodes + p1_lin];
+  const double V5 = G.Vp * 4.0 * kPi;
+  it.coef = (A.symmetric ? ch.w : ch.sigma) * V5 / (double)A.n_samples;
+}
+
+// 1 / ((2 pi)^3 * 2 * 2 * 16 pi^2): two-body phase space |p*|/(16 pi^2 sqrt s),
+// k2 measure d^3k2/((2 pi)^3 2 E2) and 1/(2 E1) of Eq. C_a_b
+constexpr double kNorm = 1.0 / (8.0 * kPi * kPi * kPi * 4.0 * 16.0 * kPi * kPi);
+
+// Per-sample value (without the bracket) and the bracket, in precision R.
+template <typename R>
+__device__ __forceinline__ R weight_no_bracket(const Item& it, const Geo& g, int row, double g4) {
+  const R m = matrix_element<R>(row, (R)g.s, (R)g.t, (R)g.u, (R)it.mu);
+  const R pre = (R)(it.coef * g4 * kNorm / it.E1) * (R)g.pstar * (R)g.rs / (R)g.E2;
+  return m * pre;
+}
+
+__device__ __forceinline__ bool is_gluon(int sp) { return sp == kGluon; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// FP64 kernel: f read from the FP64 field in global memory, deposits as FP64
+// atomics into the output.  This is the reference-precision path.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void collide_f64_kernel(CollideArgs A) {
+  const Grid& G = A.G;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int nwaves = gridDim.x * blockDim.x / kWave;
+  const long long n_items = (long long)G.cells * A.n_group * G.nodes;
+  for (long long w = wave; w < n_items; w += nwaves) {
+    const int p1_lin = (int)(w % G.nodes);
+    const int gi = (int)((w / G.nodes) % A.n_group);
+    const int cell = (int)(w / ((long long)G.nodes * A.n_group));
+    const int ci = A.group[gi];
+    const Channel ch = A.chans[ci];
+    Item it;
+    load_item(it, A, ch, cell, p1_lin);
+    if (!(it.E1 > 0.0)) {  // massless p = 0 node: zero measure
+      if (lane == 0 && A.items) A.items[((size_t)cell * A.n_channels + ci) * G.nodes + p1_lin] = 0.0;
+      continue;
+    }
+    const double* fc[4];
+    double* Ac[4];
+    double* Sc[4];
+    for (int p = 0; p < 4; ++p) {
+      fc[p] = A.f64 + ((size_t)ch.sp[p] * G.cells + cell) * G.nodes;
+      Ac[p] = A.A + ((size_t)ch.sp[p] * G.cells + cell) * G.nodes;
+      Sc[p] = A.scale ? A.scale + ((size_t)ch.sp[p] * G.cells + cell) * G.nodes : nullptr;
+    }
+    const bool g1 = is_gluon(ch.sp[0]), g2 = is_gluon(ch.sp[1]);
+    const bool g3 = is_gluon(ch.sp[2]), g4 = is_gluon(ch.sp[3]);
+    const double F1 = g1 ? 1.0 + it.f1 : 1.0 - it.f1;
+    double dsum = 0.0, ssum = 0.0;
+    int n_ok = 0;
+    for (int s = lane; s < A.n_samples; s += kWave) {
+      uint32_t x0 = (uint32_t)s, x1 = (uint32_t)p1_lin, x2 = (uint32_t)cell, x3 = ((uint32_t)ch.code << 8);
+      philox4x32_10(x0, x1, x2, x3, A.key0, A.key1);
+      double u[5];
+      five_uniforms(x0, x1, x2, x3, u);
+      Geo g;
+      if (!geometry(it, G, u, g)) continue;
+      ++n_ok;
+      const double wnb = weight_no_bracket<double>(it, g, ch.row, G.g4);
+      const Stencil<double> s2 = make_stencil<double>(g.p2, G);
+      const Stencil<double> s3 = make_stencil<double>(g.p3, G);
+      const Stencil<double> s4 = make_stencil<double>(g.p4, G);
+      const double f2 = interpolate<double>(fc[1], s2, G.ox, G.oy);
+      const double f3 = interpolate<double>(fc[2], s3, G.ox, G.oy);
+      const double f4 = interpolate<double>(fc[3], s4, G.ox, G.oy);
+      const double F2 = g2 ? 1.0 + f2 : 1.0 - f2;
+      const double F3 = g3 ? 1.0 + f3 : 1.0 - f3;
+      const double F4 = g4 ? 1.0 + f4 : 1.0 - f4;
+      const double gain = f3 * f4 * F1 * F2, loss = it.f1 * f2 * F3 * F4;
+      const double v = wnb * (gain - loss);
+      dsum += v;
+      const double vs = fabs(wnb) * (gain + loss);
+      ssum += vs;
+      if (A.symmetric) {
+        deposit<double, double>(Ac[1], s2, v, G.ox, G.oy);
+        deposit<double, double>(Ac[2], s3, -v, G.ox, G.oy);
+        deposit<double, double>(Ac[3], s4, -v, G.ox, G.oy);
+        if (A.scale) {
+          deposit<double, double>(Sc[1], s2, vs, G.ox, G.oy);
+          deposit<double, double>(Sc[2], s3, vs, G.ox, G.oy);
+          deposit<double, double>(Sc[3], s4, vs, G.ox, G.oy);
+        }
+      }
+    }
+    dsum = wave_sum(dsum);
+    if (A.scale) ssum = wave_sum(ssum);
+    const int ok_total = wave_count(n_ok);
+    if (lane == 0) {
+      if (A.n_accepted) atomicAdd(A.n_accepted, (unsigned long long)ok_total);
+      atomicAdd(Ac[0] + p1_lin, dsum);
+      if (A.scale) atomicAdd(Sc[0] + p1_lin, ssum);
+      if (A.items) A.items[((size_t)cell * A.n_channels + ci) * G.nodes + p1_lin] = dsum;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 kernel.  A workgroup owns (cell, channel, a chunk of observed nodes).
+// LDS holds FP64 accumulators for the first `lds_acc` deposit slots of the
+// channel and FP32 f tiles for the first `lds_tiles` slots; slots beyond those
+// deposit with FP64 atomics into the output / read f from global memory.  The
+// accumulators are flushed into the FP64 output once per workgroup.
+// ---------------------------------------------------------------------------
+template <bool kTilesLds, typename R>
+__device__ __forceinline__ R interp_slot(int k, int n_tiles, const float* tiles, const float* __restrict__ f32,
+                                         const size_t* goff, const Stencil<R>& st, int nodes, int ox, int oy) {
+  if (kTilesLds || k < n_tiles) return interpolate<R>(tiles + k * nodes, st, ox, oy);
+  return interpolate<R>(f32 + goff[k], st, ox, oy);
+}
+
+// The corner values are split in FP64 from the FP32 value and weights (both
+// convert exactly), so the deposits of a sample cancel to FP64 rounding.
+__device__ __forceinline__ Stencil<double> widen(const Stencil<float>& st) {
+  return Stencil<double>{st.base, (double)st.wx, (double)st.wy, (double)st.wz};
+}
+
+__device__ __forceinline__ void deposit_slot(int k, int n_acc, double* acc, double* __restrict__ out,
+                                             const size_t* goff, const Stencil<float>& st, float v, int nodes,
+                                             int ox, int oy) {
+  if (k < n_acc) deposit<double, double>(acc + k * nodes, widen(st), (double)v, ox, oy);
+  else deposit<double, double>(out + goff[k], widen(st), (double)v, ox, oy);
+}
+
+template <bool kSym, bool kScale, bool kTilesLds>
+__global__ __launch_bounds__(512) void collide_f32_kernel(CollideArgs A) {
+  extern __shared__ double lds[];
+  const Grid& G = A.G;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  const int chunk = blockIdx.x % A.n_chunks;
+  const int gi = (blockIdx.x / A.n_chunks) % A.n_group;
+  const int cell = blockIdx.x / (A.n_chunks * A.n_group);
+  const int ci = A.group[gi];
+  const Channel ch = A.chans[ci];
+  const int nslot = ch.nslot;
+  const int nodes = G.nodes;
+  const int n_acc = kSym ? min(nslot, A.lds_acc) : 0;
+  const int n_tiles = min(nslot, A.lds_tiles);
+  double* acc = lds;                                          // [n_acc][nodes]
+  float* tiles = reinterpret_cast<float*>(lds + (size_t)n_acc * nodes);  // [n_tiles][nodes]
+  size_t goff[3];  // offsets of the slots' (species, cell) rows in f32 and A
+  for (int k = 0; k < 3; ++k) {
+    const int sp = k < nslot ? ch.slot_sp[k] : ch.slot_sp[0];
+    goff[k] = ((size_t)sp * G.cells + cell) * nodes;
+  }
+  for (int i = threadIdx.x; i < n_acc * nodes; i += blockDim.x) acc[i] = 0.0;
+  for (int k = 0; k < n_tiles; ++k)
+    for (int i = threadIdx.x; i < nodes; i += blockDim.x) tiles[k * nodes + i] = A.f32[goff[k] + i];
+  __syncthreads();
+  const int k2 = ch.pos_slot[0], k3 = ch.pos_slot[1], k4 = ch.pos_slot[2];
+  const bool g1 = is_gluon(ch.sp[0]), g2 = is_gluon(ch.sp[1]);
+  const bool g3 = is_gluon(ch.sp[2]), g4 = is_gluon(ch.sp[3]);
+  const int first = chunk * A.chunk_items;
+  const int last = min(first + A.chunk_items, nodes);
+  for (int p1_lin = first + wid; p1_lin < last; p1_lin += nw) {
+    Item it;
+    load_item(it, A, ch, cell, p1_lin);
+    if (!(it.E1 > 0.0)) {  // massless p = 0 node: zero measure
+      if (lane == 0 && A.items) A.items[((size_t)cell * A.n_channels + ci) * nodes + p1_lin] = 0.0;
+      continue;
+    }
+    const float f1 = (float)it.f1;
+    const float F1 = g1 ? 1.0f + f1 : 1.0f - f1;
+    double dsum = 0.0, ssum = 0.0;
+    int n_ok = 0;
+    for (int s = lane; s < A.n_samples; s += kWave) {
+      uint32_t x0 = (uint32_t)s, x1 = (uint32_t)p1_lin, x2 = (uint32_t)cell, x3 = ((uint32_t)ch.code << 8);
+      philox4x32_10(x0, x1, x2, x3, A.key0, A.key1);
+      double u[5];
+      five_uniforms(x0, x1, x2, x3, u);
+      Geo g;
+      if (!geometry(it, G, u, g)) continue;
+      ++n_ok;
+      const float wnb = weight_no_bracket<float>(it, g, ch.row, G.g4);
+      const Stencil<float> s2 = make_stencil<float>(g.p2, G);
+      const Stencil<float> s3 = make_stencil<float>(g.p3, G);
+      const Stencil<float> s4 = make_stencil<float>(g.p4, G);
+      const float f2 = interp_slot<kTilesLds, float>(k2, n_tiles, tiles, A.f32, goff, s2, nodes, G.ox, G.oy);
+      const float f3 = interp_slot<kTilesLds, float>(k3, n_tiles, tiles, A.f32, goff, s3, nodes, G.ox, G.oy);
+      const float f4 = interp_slot<kTilesLds, float>(k4, n_tiles, tiles, A.f32, goff, s4, nodes, G.ox, G.oy);
+      const float F2 = g2 ? 1.0f + f2 : 1.0f - f2;
+      const float F3 = g3 ? 1.0f + f3 : 1.0f - f3;
+      const float F4 = g4 ? 1.0f + f4 : 1.0f - f4;
+      const float gain = f3 * f4 * F1 * F2, loss = f1 * f2 * F3 * F4;
+      const float v = wnb * (gain - loss);
+      dsum += (double)v;
+      if (kScale) ssum += (double)(fabsf(wnb) * (gain + loss));
+      if (kSym) {
+        deposit_slot(k2, n_acc, acc, A.A, goff, s2, v, nodes, G.ox, G.oy);
+        deposit_slot(k3, n_acc, acc, A.A, goff, s3, -v, nodes, G.ox, G.oy);
+        deposit_slot(k4, n_acc, acc, A.A, goff, s4, -v, nodes, G.ox, G.oy);
+        if (kScale) {
+          const float vs = fabsf(wnb) * (gain + loss);
+          deposit<double, double>(A.scale + ((size_t)ch.sp[1] * G.cells + cell) * nodes, widen(s2), (double)vs, G.ox, G.oy);
+          deposit<double, double>(A.scale + ((size_t)ch.sp[2] * G.cells + cell) * nodes, widen(s3), (double)vs, G.ox, G.oy);
+          deposit<double, double>(A.scale + ((size_t)ch.sp[3] * G.cells + cell) * nodes, widen(s4), (double)vs, G.ox, G.oy);
+        }
+      }
+    }
+    dsum = wave_sum(dsum);
+    if (kScale) ssum = wave_sum(ssum);
+    const int ok_total = wave_count(n_ok);
+    if (lane == 0) {
+      if (A.n_accepted) atomicAdd(A.n_accepted, (unsigned long long)ok_total);
+      atomicAdd(A.A + ((size_t)ch.sp[0] * G.cells + cell) * nodes + p1_lin, dsum);
+      if (kScale) atomicAdd(A.scale + ((size_t)ch.sp[0] * G.cells + cell) * nodes + p1_lin, ssum);
+      if (A.items) A.items[((size_t)cell * A.n_channels + ci) * nodes + p1_lin] = dsum;
+    }
+  }
+  if (n_acc > 0) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < n_acc * nodes; i += blockDim.x) {
+      const double v = acc[i];
+      if (v != 0.0) {
+        const int k = i / nodes;
+        atomicAdd(A.A + goff[k] + (i - k * nodes), v);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_collide_f64(const CollideArgs& a, hipStream_t stream) {
+  const long long items = (long long)a.G.cells * a.n_group * a.G.nodes;
+  const int threads = 256;
+  long long blocks = (items * kWave + threads - 1) / threads;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(collide_f64_kernel, dim3((unsigned)blocks), dim3(threads), 0, stream, a);
+  return hipGetLastError();
+}
+
+template <bool kSym, bool kScale>
+void launch_f32_variant(const CollideArgs& a, bool tiles_lds, dim3 grid, dim3 block, size_t lds, hipStream_t st) {
+  if (tiles_lds)
+    hipLaunchKernelGGL((collide_f32_kernel<kSym, kScale, true>), grid, block, lds, st, a);
+  else
+    hipLaunchKernelGGL((collide_f32_kernel<kSym, kScale, false>), grid, block, lds, st, a);
+}
+
+hipError_t launch_collide_f32(const CollideArgs& a, int nslot, hipStream_t stream) {
+  const int threads = 512;
+  const int n_acc = a.symmetric ? std::min(nslot, a.lds_acc) : 0;
+  const int n_tiles = std::min(nslot, a.lds_tiles);
+  const bool tiles_lds = n_tiles == nslot;
+  const size_t lds = (size_t)n_acc * a.G.nodes * sizeof(double) + (size_t)n_tiles * a.G.nodes * sizeof(float);
+  const long long blocks = (long long)a.G.cells * a.n_group * a.n_chunks;
+  if (blocks <= 0) return hipSuccess;
+  const dim3 grid((unsigned)blocks), block(threads);
+  if (a.symmetric) {
+    if (a.scale) launch_f32_variant<true, true>(a, tiles_lds, grid, block, lds, stream);
+    else launch_f32_variant<true, false>(a, tiles_lds, grid, block, lds, stream);
+  } else {
+    if (a.scale) launch_f32_variant<false, true>(a, tiles_lds, grid, block, lds, stream);
+    else launch_f32_variant<false, false>(a, tiles_lds, grid, block, lds, stream);
+  }
+  return hipGetLastError();
+}
+
+hipError_t set_collide_lds_limit(size_t bytes) {
+  // Raising the per-kernel dynamic LDS limit is only needed (and only
+  // accepted) above the runtime's default; a refusal leaves the default, which
+  // the planner's budget then has to respect, so it is not an error here.
+  const void* fns[8] = {(const void*)collide_f32_kernel<true, true, true>,
+                        (const void*)collide_f32_kernel<true, false, true>,
+                        (const void*)collide_f32_kernel<false, true, true>,
+                        (const void*)collide_f32_kernel<false, false, true>,
+                        (const void*)collide_f32_kernel<true, true, false>,
+                        (const void*)collide_f32_kernel<true, false, false>,
+                        (const void*)collide_f32_kernel<false, true, false>,
+                        (const void*)collide_f32_kernel<false, false, false>};
+  for (const void* fn : fns) {
+    hipFuncAttributes attr;
+    if (hipFuncGetAttributes(&attr, fn) != hipSuccess) return hipGetLastError();
+    if (attr.maxDynamicSharedSizeBytes >= (int)bytes) continue;
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) {
+      (void)hipGetLastError();
+    }
+  }
+  return hipSuccess;
+}
+
+}  // namespace qgbe

@@ -1,0 +1,27 @@
+// Launch interface of the field kernels (masses, drift + update, observables).
+#pragma once
+
+#include "qgbe_common.h"
+
+namespace qgbe {
+
+struct Mass7 {
+  double v[kSpecies];
+};
+
+// Observables layout in `out` (length observables_len): per species
+// [N, E, Px, Py, Pz] (7 x 5), then min f, max fermion f, non-finite count.
+constexpr int observables_len = kSpecies * 5 + 3;
+
+hipError_t launch_masses(const Grid& G, const double* f, const double* lag, double* mass2, hipStream_t st);
+hipError_t launch_const_masses(const Grid& G, const Mass7& m, double* mass2, hipStream_t st);
+hipError_t launch_update(const Grid& G, const double* f, const double* A, const double* mass2, double dt,
+                         int scheme, double* f_out, float* f32, hipStream_t st);
+size_t observables_scratch(const Grid& G);
+hipError_t launch_observables(const Grid& G, const double* f, const double* mass2, double* scratch,
+                              double* out, hipStream_t st);
+hipError_t launch_to_f32(const double* src, float* dst, size_t n, hipStream_t st);
+hipError_t launch_fill(double* dst, double v, size_t n, hipStream_t st);
+hipError_t launch_zero_u64(unsigned long long* dst, hipStream_t st);
+
+}  // namespace qgbe

@@ -1,0 +1,310 @@
+// Field kernels around the collision term: thermal masses (Eq. mg, Eq. mq),
+// the drift of Eq. left handside with the forward-Euler update (Sec. III),
+// and the FP64 bookkeeping (Eq. particle numbers, Eq. energy momentum tensor).
+// All of them are HBM-bound stencils or reductions in FP64.
+#include <hip/hip_runtime.h>
+
+#include "field.h"
+
+namespace qgbe {
+namespace {
+
+constexpr int kBlock = 256;
+
+__device__ __forceinline__ void node_p(const Grid& G, int node, double p[3]) {
+  const int iz = node % G.np[2];
+  const int iy = (node / G.np[2]) % G.np[1];
+  const int ix = node / (G.np[2] * G.np[1]);
+  p[0] = -G.ph[0] + (ix + 0.5) * G.dp[0];
+  p[1] = -G.ph[1] + (iy + 0.5) * G.dp[1];
+  p[2] = -G.ph[2] + (iz + 0.5) * G.dp[2];
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  const int w = threadIdx.x / 64, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x / 64); ++i) t += sh[i];
+  return t;  // valid in thread 0
+}
+
+// One block per cell.  I_Y = sum_p dV/(2pi)^3 f_Y / (2 E_Y), E_Y from the
+// lagged masses (or |p| when there are none; a node at p = 0 then adds 0).
+__global__ __launch_bounds__(kBlock) void mass_kernel(Grid G, const double* __restrict__ f,
+                                                      const double* __restrict__ lag, double* mass2) {
+  __shared__ double sh[kBlock / 64];
+  const int cell = blockIdx.x;
+  const double meas = G.dp[0] * G.dp[1] * G.dp[2] / (8.0 * kPi * kPi * kPi);
+  double I[kSpecies];
+  for (int sp = 0; sp < kSpecies; ++sp) {
+    const double m2 = lag ? lag[sp * G.cells + cell] : 0.0;
+    const double* fc = f + ((size_t)sp * G.cells + cell) * G.nodes;
+    double acc = 0.0;
+    for (int node = threadIdx.x; node < G.nodes; node += blockDim.x) {
+      double p[3];
+      node_p(G, node, p);
+      const double E = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2] + m2);
+      if (E > 0.0) acc += fc[node] / (2.0 * E);
+    }
+    I[sp] = block_sum(acc, sh) * meas;
+  }
+  if (threadIdx.x == 0) {
+    // SU(3): dA = 8, CA = 3, CF = 4/3; N_g = 16, N_q = 6
+    const double CF = 4.0 / 3.0;
+    double q = 0.0;
+    for (int i = 0; i < 3; ++i) q += 6.0 * CF * (I[i] + I[i + 3]);
+    mass2[kGluon * G.cells + cell] = (2.0 * G.g2 / 8.0) * (16.0 * 3.0 * I[kGluon] + q);
+    for (int i = 0; i < 3; ++i) {
+      const double mq = 2.0 * CF * G.g2 * (2.0 * I[kGluon] + I[i] + I[i + 3]);
+      mass2[i * G.cells + cell] = mq;
+      mass2[(i + 3) * G.cells + cell] = mq;
+    }
+  }
+}
+
+__global__ void const_mass_kernel(Grid G, Mass7 m, double* mass2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < kSpecies * G.cells) mass2[i] = m.v[i / G.cells];
+}
+
+__device__ __forceinline__ int shift_cell(const Grid& G, int cell, int axis, int d) {
+  int id[3] = {cell / (G.nx[1] * G.nx[2]), (cell / G.nx[2]) % G.nx[1], cell % G.nx[2]};
+  id[axis] = (id[axis] + d + G.nx[axis]) % G.nx[axis];
+  return (id[0] * G.nx[1] + id[1]) * G.nx[2] + id[2];
+}
+
+__device__ __forceinline__ int shift_node(const Grid& G, int node, int axis, int d) {
+  int id[3] = {node / (G.np[1] * G.np[2]), (node / G.np[2]) % G.np[1], node % G.np[2]};
+  id[axis] = (id[axis] + d + G.np[axis]) % G.np[axis];
+  return (id[0] * G.np[1] + id[1]) * G.np[2] + id[2];
+}
+
+__device__ __forceinline__ double energy(const Grid& G, const double* mass2, int sp, int cell, int node) {
+  double p[3];
+  node_p(G, node, p);
+  return sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2] + mass2[sp * G.cells + cell]);
+}
+
+__device__ __forceinline__ double upwind(double vel, double f_left, double f_right) {
+  return vel > 0.0 ? vel * f_left : vel * f_right;
+}
+
+// D[f] at (sp, cell, node), flux form with periodic boundaries.
+__device__ double drift_at(const Grid& G, const double* f, const double* mass2, int sp, int cell,
+                           int node, int scheme) {
+  const double* F = f + (size_t)sp * G.cells * G.nodes;
+  double p[3];
+  node_p(G, node, p);
+  double D = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    if (G.nx[a] == 1) continue;  // a single periodic cell has no gradient
+    const int xp = shift_cell(G, cell, a, +1), xm = shift_cell(G, cell, a, -1);
+    const int pp = shift_node(G, node, a, +1), pm = shift_node(G, node, a, -1);
+    const double Ec = energy(G, mass2, sp, cell, node);
+    const double Exp = energy(G, mass2, sp, xp, node), Exm = energy(G, mass2, sp, xm, node);
+    const double inv2dx = 0.5 / G.dx[a];
+    if (scheme == 0) {
+      const double vc = p[a] / Ec, vp = p[a] / Exp, vm = p[a] / Exm;
+      const double fR = upwind(0.5 * (vc + vp), F[(size_t)cell * G.nodes + node], F[(size_t)xp * G.nodes + node]);
+      const double fL = upwind(0.5 * (vm + vc), F[(size_t)xm * G.nodes + node], F[(size_t)cell * G.nodes + node]);
+      D += (fR - fL) / G.dx[a];
+      // p-advection with the force -dE/dx_a (central in x)
+      const double Fc = -(Exp - Exm) * inv2dx;
+      const double Fp = -(energy(G, mass2, sp, xp, pp) - energy(G, mass2, sp, xm, pp)) * inv2dx;
+      const double Fm = -(energy(G, mass2, sp, xp, pm) - energy(G, mass2, sp, xm, pm)) * inv2dx;
+      const double gR = upwind(0.5 * (Fc + Fp), F[(size_t)cell * G.nodes + node], F[(size_t)cell * G.nodes + pp]);
+      const double gL = upwind(0.5 * (Fm + Fc), F[(size_t)cell * G.nodes + pm], F[(size_t)cell * G.nodes + node]);
+      D += (gR - gL) / G.dp[a];
+    } else {
+      D += (p[a] * F[(size_t)xp * G.nodes + node] / Exp - p[a] * F[(size_t)xm * G.nodes + node] / Exm) * inv2dx;
+      const double dEp = (energy(G, mass2, sp, xp, pp) - energy(G, mass2, sp, xm, pp)) * inv2dx;
+      const double dEm = (energy(G, mass2, sp, xp, pm) - energy(G, mass2, sp, xm, pm)) * inv2dx;
+      D -= (F[(size_t)cell * G.nodes + pp] * dEp - F[(size_t)cell * G.nodes + pm] * dEm) * (0.5 / G.dp[a]);
+    }
+  }
+  return D;
+}
+
+// f_out = f + dt (A / (N_Y hbar c) - D[f]) for evolving species; frozen otherwise.
+__global__ __launch_bounds__(kBlock) void update_kernel(Grid G, const double* __restrict__ f,
+                                                        const double* __restrict__ A,
+                                                        const double* __restrict__ mass2, double dt,
+                                                        int scheme, double* __restrict__ f_out,
+                                                        float* __restrict__ f32) {
+  const size_t total = (size_t)kSpecies * G.cells * G.nodes;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+    const int sp = (int)(i / ((size_t)G.cells * G.nodes));
+    const size_t rem = i - (size_t)sp * G.cells * G.nodes;
+    const int cell = (int)(rem / G.nodes), node = (int)(rem % G.nodes);
+    double v = f[i];
+    if ((G.species_mask >> sp) & 1u) {
+      const double D = drift_at(G, f, mass2, sp, cell, node, scheme);
+      v += dt * (A[i] / (degeneracy(sp) * kHbarC) - D);
+    }
+    f_out[i] = v;
+    f32[i] = (float)v;
+  }
+}
+
+// Observables: per species N, E, P (3), then min f and max fermion f, and a
+// non-finite counter.  Stage 1: per-block partials; stage 2: one block.
+constexpr int kObs = kSpecies * 5;
+
+__global__ __launch_bounds__(kBlock) void observables_partial(Grid G, const double* __restrict__ f,
+                                                              const double* __restrict__ mass2,
+                                                              double* partial) {
+  __shared__ double sh[kBlock / 64];
+  const size_t per = (size_t)G.cells * G.nodes;
+  double minf = 1e300, maxq = -1e300, bad = 0.0;
+  for (int sp = 0; sp < kSpecies; ++sp) {
+    double N = 0.0, E = 0.0, P0 = 0.0, P1 = 0.0, P2 = 0.0;
+    const bool evolve = (G.species_mask >> sp) & 1u;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < per; i += (size_t)gridDim.x * blockDim.x) {
+      const int cell = (int)(i / G.nodes), node = (int)(i % G.nodes);
+      const double fv = f[(size_t)sp * per + i];
+      double p[3];
+      node_p(G, node, p);
+      const double En = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2] + mass2[sp * G.cells + cell]);
+      N += fv;
+      E += En * fv;
+      P0 += p[0] * fv;
+      P1 += p[1] * fv;
+      P2 += p[2] * fv;
+      if (evolve) {
+        if (!isfinite(fv)) bad += 1.0;
+        minf = fmin(minf, fv);
+        if (sp != kGluon) maxq = fmax(maxq, fv);
+      }
+    }
+    const double vals[5] = {N, E, P0, P1, P2};
+    for (int k = 0; k < 5; ++k) {
+      const double t = block_sum(vals[k], sh);
+      if (threadIdx.x == 0) partial[(size_t)blockIdx.x * (kObs + 3) + sp * 5 + k] = t;
+    }
+  }
+  // min / max over the block
+  for (int off = 32; off > 0; off >>= 1) {
+    minf = fmin(minf, __shfl_xor(minf, off, 64));
+    maxq = fmax(maxq, __shfl_xor(maxq, off, 64));
+  }
+  const double nbad = block_sum(bad, sh);
+  __shared__ double shmin[kBlock / 64], shmax[kBlock / 64];
+  const int w = threadIdx.x / 64, lane = threadIdx.x & 63;
+  if (lane == 0) { shmin[w] = minf; shmax[w] = maxq; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < (int)(blockDim.x / 64); ++i) { minf = fmin(minf, shmin[i]); maxq = fmax(maxq, shmax[i]); }
+    double* o = partial + (size_t)blockIdx.x * (kObs + 3);
+    o[kObs] = minf;
+    o[kObs + 1] = maxq;
+    o[kObs + 2] = nbad;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void observables_final(Grid G, const double* partial, int nblocks,
+                                                            double* out) {
+  __shared__ double sh[kBlock / 64];
+  const double meas = G.dx[0] * G.dx[1] * G.dx[2] * G.dp[0] * G.dp[1] * G.dp[2] / (8.0 * kPi * kPi * kPi);
+  for (int k = 0; k < kObs + 3; ++k) {
+    double v = (k == kObs) ? 1e300 : (k == kObs + 1 ? -1e300 : 0.0);
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+      const double x = partial[(size_t)b * (kObs + 3) + k];
+      if (k == kObs) v = fmin(v, x);
+      else if (k == kObs + 1) v = fmax(v, x);
+      else v += x;
+    }
+    if (k == kObs || k == kObs + 1) {
+      for (int off = 32; off > 0; off >>= 1) {
+        const double o = __shfl_xor(v, off, 64);
+        v = (k == kObs) ? fmin(v, o) : fmax(v, o);
+      }
+      __shared__ double shm[kBlock / 64];
+      const int w = threadIdx.x / 64, lane = threadIdx.x & 63;
+      __syncthreads();
+      if (lane == 0) shm[w] = v;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        for (int i = 1; i < (int)(blockDim.x / 64); ++i) v = (k == kObs) ? fmin(v, shm[i]) : fmax(v, shm[i]);
+        out[k] = v;
+      }
+    } else {
+      const double t = block_sum(v, sh);
+      if (threadIdx.x == 0) out[k] = (k < kObs) ? t * degeneracy(k / 5) * meas : t;
+    }
+  }
+}
+
+__global__ void to_f32_kernel(const double* __restrict__ src, float* __restrict__ dst, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+
+__global__ void fill_kernel(double* __restrict__ dst, double v, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = v;
+}
+
+__global__ void zero_u64_kernel(unsigned long long* dst) { *dst = 0ull; }
+
+unsigned grid_for(size_t n) {
+  size_t b = (n + kBlock - 1) / kBlock;
+  if (b > 16384) b = 16384;
+  return (unsigned)(b ? b : 1);
+}
+
+}  // namespace
+
+hipError_t launch_masses(const Grid& G, const double* f, const double* lag, double* mass2, hipStream_t st) {
+  hipLaunchKernelGGL(mass_kernel, dim3(G.cells), dim3(kBlock), 0, st, G, f, lag, mass2);
+  return hipGetLastError();
+}
+
+hipError_t launch_const_masses(const Grid& G, const Mass7& m, double* mass2, hipStream_t st) {
+  const int n = kSpecies * G.cells;
+  hipLaunchKernelGGL(const_mass_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, G, m, mass2);
+  return hipGetLastError();
+}
+
+hipError_t launch_update(const Grid& G, const double* f, const double* A, const double* mass2, double dt,
+                         int scheme, double* f_out, float* f32, hipStream_t st) {
+  const size_t n = (size_t)kSpecies * G.cells * G.nodes;
+  hipLaunchKernelGGL(update_kernel, dim3(grid_for(n)), dim3(kBlock), 0, st, G, f, A, mass2, dt, scheme, f_out, f32);
+  return hipGetLastError();
+}
+
+int observables_blocks(const Grid& G) {
+  const size_t per = (size_t)G.cells * G.nodes;
+  size_t b = (per + kBlock - 1) / kBlock;
+  return (int)(b > 512 ? 512 : (b ? b : 1));
+}
+
+size_t observables_scratch(const Grid& G) { return (size_t)observables_blocks(G) * (kObs + 3); }
+
+hipError_t launch_observables(const Grid& G, const double* f, const double* mass2, double* scratch,
+                              double* out, hipStream_t st) {
+  const int nb = observables_blocks(G);
+  hipLaunchKernelGGL(observables_partial, dim3(nb), dim3(kBlock), 0, st, G, f, mass2, scratch);
+  hipLaunchKernelGGL(observables_final, dim3(1), dim3(kBlock), 0, st, G, scratch, nb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_f32(const double* src, float* dst, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(to_f32_kernel, dim3(grid_for(n)), dim3(kBlock), 0, st, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(double* dst, double v, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(kBlock), 0, st, dst, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u64(unsigned long long* dst, hipStream_t st) {
+  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, st, dst);
+  return hipGetLastError();
+}
+
+}  // namespace qgbe

@@ -179,3 +179,17 @@ def random_mog_table(seed: int, rows: int, K: int = 8, alpha: float = 0.1,
     mu = rng.normal(0.0, mu_scale, size=(rows, K, 5)).astype(np.float32)
     sigma = np.exp(rng.uniform(log_sigma[0], log_sigma[1], size=(rows, K, 5))).astype(np.float32)
     return thr, mu, sigma
+
+
+def random_mlp_params(seed: int, n_in: int = 8, hidden: int = 128, n_out: int = 88,
+                      head_scale: float = 0.1) -> np.ndarray:
+    """Flat FP32 parameter vector W1, b1, W2, b2, W3, b3 (row-major [in][out]),
+    He-style initialisation with a small head."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    W1 = rng.normal(0.0, np.sqrt(2.0 / n_in), (n_in, hidden))
+    b1 = rng.normal(0.0, 0.05, hidden)
+    W2 = rng.normal(0.0, np.sqrt(2.0 / hidden), (hidden, hidden))
+    b2 = rng.normal(0.0, 0.05, hidden)
+    W3 = rng.normal(0.0, head_scale * np.sqrt(1.0 / hidden), (hidden, n_out))
+    b3 = rng.normal(0.0, 0.05, n_out)
+    return np.concatenate([a.ravel() for a in (W1, b1, W2, b2, W3, b3)]).astype(np.float32)

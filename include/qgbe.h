@@ -198,6 +198,72 @@ qgbe_status qgbe_observables(qgbe_ctx* ctx, qgbe_stats* st);
 qgbe_status qgbe_set_proposal_table(qgbe_ctx* ctx, int32_t K, const uint32_t* thr,
                                     const float* mu, const float* sigma, int32_t on_device);
 
+/* ---- the learned proposal (a network that writes the proposal table) ---- */
+/*
+ * Network: x (8 inputs) -> Linear 8x128 -> SiLU -> Linear 128x128 -> SiLU ->
+ * Linear 128x88 = head (8 mixture logits, 8x5 locations, 8x5 log scales of a
+ * logistic-normal mixture over the five unit-cube variables).  Products run
+ * as BF16 x BF16 -> FP32 matrix-core GEMMs; master weights, Adam moments and
+ * the head arithmetic are FP32.  The weights are the flat FP32 vector
+ * W1 [8][128], b1 [128], W2 [128][128], b2 [128], W3 [128][88], b3 [88]
+ * (row-major [in][out]), QGBE_MLP_PARAMS floats.
+ * Inputs x of the work item (channel c, observed node p1, cell masses):
+ *   p1x/Px, p1y/Py, p1z/Pz, |p1|/|P|, E1/|P|, m_g^2/|P|^2,
+ *   species/3 - 1, 2c/(channels-1) - 1        (P = p_half, |P| its norm).
+ * The proposal is unbiased for any weights (importance weights 1/q with a
+ * defensive uniform share); training only lowers the variance.
+ */
+#define QGBE_MLP_PARAMS 29016
+#define QGBE_MLP_BATCH 16384   /* maximum rows of one qgbe_mlp_loss_grad call */
+
+typedef struct {
+  int32_t epochs;          /* passes over the recorded rows                  */
+  int32_t batch;           /* rows per Adam step (<= QGBE_MLP_BATCH)         */
+  float lr;                /* initial learning rate                          */
+  float lr_final;          /* learning rate at the end (cosine decay)        */
+  float alpha;             /* defensive uniform share of the table, (0,1)    */
+  uint64_t seed;           /* shuffling seed                                 */
+} qgbe_train_cfg;
+
+/* Copy the FP32 weights in (resets the Adam moments) or out. n must equal
+ * QGBE_MLP_PARAMS.  Host pointers. */
+qgbe_status qgbe_proposal_set_weights(qgbe_ctx* ctx, const float* w, int64_t n);
+qgbe_status qgbe_proposal_get_weights(qgbe_ctx* ctx, float* w, int64_t n);
+
+/* Network forward pass: X [rows][8] FP32 -> head Y [rows][88] FP32. */
+qgbe_status qgbe_mlp_forward(qgbe_ctx* ctx, const float* X, int64_t rows, float* Y, int32_t on_device);
+
+/* Weighted negative log-likelihood of the mixture head and its gradient:
+ * X [rows][8], yw [rows][6] = (logit u (5), weight); loss = -sum w log q /
+ * sum w; grad [QGBE_MLP_PARAMS] FP32; rows <= QGBE_MLP_BATCH. */
+qgbe_status qgbe_mlp_loss_grad(qgbe_ctx* ctx, const float* X, const float* yw, int64_t rows, float* grad,
+                               double* loss, int32_t on_device);
+
+/* Conditioning inputs of every (channel, node) row at cell 0 with the masses
+ * of the last collision term or step: X [channels*nodes][8]. */
+qgbe_status qgbe_proposal_features(qgbe_ctx* ctx, float* X, int32_t on_device);
+
+/* Record training rows from uniform samples of the current f: for every
+ * item_stride-th work item (cell, channel, node; node fastest), n_per_item
+ * samples, each row [x (8), logit u (5), |sample value|] (14 FP32).
+ * *n_rows receives the row count; rows must hold max_rows rows. */
+qgbe_status qgbe_record_samples(qgbe_ctx* ctx, int32_t n_per_item, int64_t item_stride, float* rows,
+                                int64_t max_rows, int64_t* n_rows, int32_t on_device);
+
+/* Train the network on recorded rows ([n][14], as qgbe_record_samples writes)
+ * with Adam on device; epoch_loss [epochs] (may be NULL) receives the mean
+ * training loss of each epoch.  Then builds the proposal table. */
+qgbe_status qgbe_train_proposal(qgbe_ctx* ctx, const float* rows, int64_t n, const qgbe_train_cfg* cfg,
+                                double* epoch_loss, int32_t on_device);
+
+/* Evaluate the network on every (channel, node) row and install the result
+ * as the proposal table (defensive share alpha). */
+qgbe_status qgbe_proposal_build_table(qgbe_ctx* ctx, float alpha);
+
+/* Copy the installed proposal table out (thr [rows][K], mu, sigma
+ * [rows][K][5], rows = channels*nodes), K written to *K. */
+qgbe_status qgbe_get_proposal_table(qgbe_ctx* ctx, int32_t* K, uint32_t* thr, float* mu, float* sigma);
+
 /* ---- host-only helpers (no device needed) ------------------------------- */
 
 /* The channel table the library builds for the masks: rows [n][5] =

@@ -8,16 +8,15 @@
 #include <string>
 #include <vector>
 
-#include "collide.h"
-#include "field.h"
-#include "qgbe.h"
-#include "qgbe_common.h"
+#include "context.h"
 
 using namespace qgbe;
 
 namespace {
-
 thread_local std::string g_error;
+}  // namespace
+
+namespace qgbe {
 
 qgbe_status fail(qgbe_status s, const std::string& msg) {
   g_error = msg;
@@ -25,71 +24,53 @@ qgbe_status fail(qgbe_status s, const std::string& msg) {
 }
 
 qgbe_status hip_fail(hipError_t e, const char* what) {
-  return fail(e == hipErrorOutOfMemory ? QGBE_ENOMEM : QGBE_EDEVICE,
-              std::string(what) + ": " + hipGetErrorString(e));
+  return fail(e == hipErrorOutOfMemory ? QGBE_ENOMEM : QGBE_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
-
-#define HIP_TRY(expr, what)                    \
-  do {                                         \
-    hipError_t _e = (expr);                    \
-    if (_e != hipSuccess) return hip_fail(_e, what); \
-  } while (0)
-
-// LDS kept free for the collision kernel's static arrays
-constexpr size_t kStaticLds = 1024;
-
-// Channels of the FP32 kernel grouped by their number of deposit slots.
-struct Group {
-  int start, count;   // range in the group index array
-  int nslot;          // distinct species at positions 2..4
-  int lds_acc;        // FP64 accumulators staged in LDS
-  int lds_tiles;      // FP32 f tiles staged in LDS
-};
-
-}  // namespace
-
-struct qgbe_ctx {
-  qgbe_grid_desc d{};
-  Grid G{};
-  hipStream_t stream = nullptr;
-  int nch = 0;
-  std::vector<Channel> chans;
-  std::vector<int> group_index;
-  std::vector<Group> groups;
-  Channel* d_chans = nullptr;
-  int* d_groups = nullptr;
-  int* d_all = nullptr;            // identity channel list (FP64 kernel)
-  double* d_f = nullptr;
-  double* d_f_next = nullptr;
-  float* d_f32 = nullptr;
-  double* d_mass2 = nullptr;
-  double* d_lag = nullptr;
-  bool has_lag = false;
-  double* d_A = nullptr;
-  double* d_obs_scratch = nullptr;
-  double* d_obs = nullptr;
-  unsigned long long* d_count = nullptr;
-  uint32_t step = 0;
-  int K = 0;
-  uint32_t* d_thr = nullptr;
-  float* d_mu = nullptr;
-  float* d_sigma = nullptr;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-  size_t ws = 0;
-  size_t lds_bytes = 0;            // dynamic LDS available per workgroup
-};
-
-namespace {
 
 size_t field_len(const qgbe_ctx* c) { return (size_t)kSpecies * c->G.cells * c->G.nodes; }
 
-template <typename T>
-qgbe_status dev_alloc(qgbe_ctx* c, T** p, size_t n, const char* what) {
-  hipError_t e = hipMalloc((void**)p, n * sizeof(T));
-  if (e != hipSuccess) { *p = nullptr; return hip_fail(e, what); }
-  c->ws += n * sizeof(T);
+}  // namespace qgbe
+
+namespace qgbe {
+
+qgbe_status compute_masses(qgbe_ctx* c) {
+  if (c->d.mass_mode == QGBE_MASS_CONSTANT) {
+    Mass7 m;
+    for (int s = 0; s < kSpecies; ++s) m.v[s] = c->d.const_mass2[s];
+    HIP_TRY(launch_const_masses(c->G, m, c->d_mass2, c->stream), "constant masses");
+  } else {
+    HIP_TRY(launch_masses(c->G, c->d_f, c->has_lag ? c->d_lag : nullptr, c->d_mass2, c->stream), "masses");
+  }
+  c->masses_valid = true;
   return QGBE_OK;
 }
+
+CollideArgs base_args(qgbe_ctx* c, int n_samples, double* A, double* scale, double* items) {
+  CollideArgs a{};
+  a.G = c->G;
+  a.chans = c->d_chans;
+  a.n_channels = c->nch;
+  a.n_samples = n_samples;
+  a.symmetric = c->d.symmetric;
+  a.key0 = (uint32_t)c->d.seed;
+  a.key1 = (uint32_t)(c->d.seed >> 32) + c->step;
+  a.f64 = c->d_f;
+  a.f32 = c->d_f32;
+  a.mass2 = c->d_mass2;
+  a.A = A;
+  a.scale = scale;
+  a.items = items;
+  a.n_accepted = c->d_count;
+  a.mix_K = c->K;
+  a.mix_thr = c->d_thr;
+  a.mix_mu = c->d_mu;
+  a.mix_sigma = c->d_sigma;
+  return a;
+}
+
+}  // namespace qgbe
+
+namespace {
 
 qgbe_status validate(const qgbe_grid_desc* d) {
   if (!d) return fail(QGBE_EINVAL, "descriptor is NULL");
@@ -159,41 +140,12 @@ void plan_groups(qgbe_ctx* c) {
   }
 }
 
-qgbe_status compute_masses(qgbe_ctx* c) {
-  if (c->d.mass_mode == QGBE_MASS_CONSTANT) {
-    Mass7 m;
-    for (int s = 0; s < kSpecies; ++s) m.v[s] = c->d.const_mass2[s];
-    HIP_TRY(launch_const_masses(c->G, m, c->d_mass2, c->stream), "constant masses");
-  } else {
-    HIP_TRY(launch_masses(c->G, c->d_f, c->has_lag ? c->d_lag : nullptr, c->d_mass2, c->stream), "masses");
-  }
-  return QGBE_OK;
-}
-
-CollideArgs base_args(qgbe_ctx* c, int n_samples, double* A, double* scale, double* items) {
-  CollideArgs a{};
-  a.G = c->G;
-  a.chans = c->d_chans;
-  a.n_channels = c->nch;
-  a.n_samples = n_samples;
-  a.symmetric = c->d.symmetric;
-  a.key0 = (uint32_t)c->d.seed;
-  a.key1 = (uint32_t)(c->d.seed >> 32) + c->step;
-  a.f64 = c->d_f;
-  a.f32 = c->d_f32;
-  a.mass2 = c->d_mass2;
-  a.A = A;
-  a.scale = scale;
-  a.items = items;
-  a.n_accepted = c->d_count;
-  return a;
-}
-
 // Enqueue the collision kernels accumulating into A (zeroed by the caller).
-qgbe_status run_collide(qgbe_ctx* c, int n_samples, double* A, double* scale, double* items) {
+qgbe_status run_collide(qgbe_ctx* c, int n_samples, bool learned, double* A, double* scale, double* items) {
   HIP_TRY(launch_zero_u64(c->d_count, c->stream), "zero counter");
   if (c->nch == 0) return QGBE_OK;
   CollideArgs a = base_args(c, n_samples, A, scale, items);
+  a.learned = learned ? 1 : 0;
   const bool f64_path = c->d.precision == QGBE_FP64;
   if (f64_path) {
     a.group = c->d_all;
@@ -389,6 +341,12 @@ void qgbe_destroy(qgbe_ctx* c) {
   (void)hipFree(c->d_thr);
   (void)hipFree(c->d_mu);
   (void)hipFree(c->d_sigma);
+  {
+    MlpState& m = c->mlp;
+    void* bufs[] = {m.params, m.m, m.v, m.grad, m.pb, m.X, m.Xb, m.Z1, m.H1b, m.Z2, m.H2b, m.Y, m.dY, m.dYb,
+                    m.dH, m.dZ, m.dZb, m.yw, m.scalars, m.idx};
+    for (void* b : bufs) (void)hipFree(b);
+  }
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
   delete c;
@@ -406,6 +364,7 @@ qgbe_status qgbe_set_distribution(qgbe_ctx* c, int32_t species, const double* f,
   HIP_TRY(launch_to_f32(c->d_f, c->d_f32, field_len(c), c->stream), "f to fp32");
   if (!on_device) HIP_TRY(hipStreamSynchronize(c->stream), "synchronise");
   c->has_lag = false;
+  c->masses_valid = false;
   return QGBE_OK;
 }
 
@@ -448,7 +407,7 @@ qgbe_status qgbe_collision_term_ex(qgbe_ctx* c, int32_t n_samples, int32_t sampl
   if (!c || !A_out) return fail(QGBE_EINVAL, "NULL argument");
   if (n_samples < 1) return fail(QGBE_EINVAL, "n_samples must be >= 1");
   if (sampler != QGBE_SAMPLER_UNIFORM && sampler != QGBE_SAMPLER_LEARNED) return fail(QGBE_EINVAL, "bad sampler");
-  if (sampler == QGBE_SAMPLER_LEARNED) return fail(QGBE_EUNSUPPORTED, "learned sampler not available in this build");
+  if (sampler == QGBE_SAMPLER_LEARNED && !c->K) return fail(QGBE_ESTATE, "no proposal table installed");
   HIP_TRY(hipSetDevice(c->d.device), "hipSetDevice");
   const size_t n = field_len(c);
   double* A = on_device ? A_out : c->d_A;
@@ -471,7 +430,7 @@ qgbe_status qgbe_collision_term_ex(qgbe_ctx* c, int32_t n_samples, int32_t sampl
     if (e == hipSuccess) e = hipEventRecord(c->ev[0], c->stream);
     if (e != hipSuccess) s = hip_fail(e, "zero outputs");
   }
-  if (!s) s = run_collide(c, n_samples, A, scale, items);
+  if (!s) s = run_collide(c, n_samples, sampler == QGBE_SAMPLER_LEARNED, A, scale, items);
   if (!s) {
     hipError_t e = hipEventRecord(c->ev[1], c->stream);
     if (e == hipSuccess && !on_device)
@@ -510,7 +469,7 @@ qgbe_status qgbe_step(qgbe_ctx* c, double dt_fm, int32_t n_samples, int32_t samp
   if (!(dt_fm > 0.0) || !std::isfinite(dt_fm)) return fail(QGBE_EINVAL, "dt must be > 0");
   if (n_samples < 1 || n_steps < 0) return fail(QGBE_EINVAL, "n_samples >= 1 and n_steps >= 0 required");
   if (sampler != QGBE_SAMPLER_UNIFORM && sampler != QGBE_SAMPLER_LEARNED) return fail(QGBE_EINVAL, "bad sampler");
-  if (sampler == QGBE_SAMPLER_LEARNED) return fail(QGBE_EUNSUPPORTED, "learned sampler not available in this build");
+  if (sampler == QGBE_SAMPLER_LEARNED && !c->K) return fail(QGBE_ESTATE, "no proposal table installed");
   HIP_TRY(hipSetDevice(c->d.device), "hipSetDevice");
   const size_t n = field_len(c);
   qgbe_status result = QGBE_OK;
@@ -520,12 +479,13 @@ qgbe_status qgbe_step(qgbe_ctx* c, double dt_fm, int32_t n_samples, int32_t samp
     if (s) return s;
     HIP_TRY(launch_fill(c->d_A, 0.0, n, c->stream), "zero A");
     HIP_TRY(hipEventRecord(c->ev[0], c->stream), "event");
-    s = run_collide(c, n_samples, c->d_A, nullptr, nullptr);
+    s = run_collide(c, n_samples, sampler == QGBE_SAMPLER_LEARNED, c->d_A, nullptr, nullptr);
     if (s) return s;
     HIP_TRY(hipEventRecord(c->ev[1], c->stream), "event");
     HIP_TRY(launch_update(c->G, c->d_f, c->d_A, c->d_mass2, dt_fm, c->d.drift, c->d_f_next, c->d_f32, c->stream),
             "update");
     std::swap(c->d_f, c->d_f_next);
+    c->masses_valid = false;
     HIP_TRY(hipMemcpyAsync(c->d_lag, c->d_mass2, (size_t)kSpecies * c->G.cells * sizeof(double),
                            hipMemcpyDeviceToDevice, c->stream), "lag masses");
     c->has_lag = c->d.mass_mode == QGBE_MASS_DYNAMIC;
@@ -554,11 +514,5 @@ qgbe_status qgbe_observables(qgbe_ctx* c, qgbe_stats* st) {
   return read_stats(c, st);
 }
 
-qgbe_status qgbe_set_proposal_table(qgbe_ctx* c, int32_t K, const uint32_t* thr, const float* mu, const float* sigma,
-                                    int32_t on_device) {
-  if (!c || !thr || !mu || !sigma) return fail(QGBE_EINVAL, "NULL argument");
-  if (K < 1 || K > 16) return fail(QGBE_EINVAL, "K must be in 1..16");
-  return fail(QGBE_EUNSUPPORTED, "learned sampler not available in this build");
-}
 
 }  // extern "C"

@@ -25,10 +25,17 @@ struct CollideArgs {
   double* scale;          // optional, same shape
   double* items;          // optional [cells][n_channels][nodes]
   unsigned long long* n_accepted;  // samples above threshold and inside the box
+  int learned;            // draw from the mixture table instead of uniformly
+  int mix_K;              // mixture components
+  const uint32_t* mix_thr;   // [channels*nodes][K]
+  const float* mix_mu;       // [channels*nodes][K][5]
+  const float* mix_sigma;    // [channels*nodes][K][5]
 };
 
 hipError_t launch_collide_f64(const CollideArgs& a, hipStream_t stream);
 hipError_t launch_collide_f32(const CollideArgs& a, int nslot, hipStream_t stream);
 hipError_t set_collide_lds_limit(size_t bytes);
+hipError_t launch_record(const CollideArgs& a, int n_per_item, long long item_stride, long long n_sel, float* rows,
+                         hipStream_t stream);
 
 }  // namespace qgbe

@@ -211,6 +211,119 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// ---------------------------------------------------------------------------
+// Mixture proposal (learned sampler).  Row = (channel, observed node).
+// thr[0] = alpha 2^32 selects the defensive uniform component; component k is
+// drawn when thr[k] <= x < thr[k+1].  Its five coordinates are logistic-normal:
+// y = mu + sigma z (z from Box-Muller), u = 1/(1 + exp(-y)).  The sample
+// location is formed in FP64 (it decides the threshold and the box cut); the
+// density q(u) = alpha + sum_k pi_k prod_d N(y_d; mu, sigma)/(u_d(1-u_d)) is
+// evaluated in the kernel's precision.
+// ---------------------------------------------------------------------------
+constexpr double kTwo32 = 4294967296.0;
+constexpr double kHalfLog2Pi = 0.91893853320467274178;
+
+// Draw u (and y = logit u) for one sample from the 8 words of two Philox blocks.
+__device__ __forceinline__ void mix_draw(const uint32_t x[8], const uint32_t* __restrict__ thr,
+                                         const float* __restrict__ mu, const float* __restrict__ sg, int K,
+                                         double u[5], double y[5]) {
+  if (x[0] < thr[0]) {
+    for (int d = 0; d < 5; ++d) {
+      u[d] = unif23(x[1 + d] >> 9);
+      y[d] = log(u[d] / (1.0 - u[d]));
+    }
+    return;
+  }
+  int k = 0;
+  for (int j = 1; j < K; ++j) k = x[0] >= thr[j] ? j : k;
+  double z[6];
+  for (int pr = 0; pr < 3; ++pr) {
+    const double a1 = unif23(x[1 + 2 * pr] >> 9), a2 = unif23(x[2 + 2 * pr] >> 9);
+    const double r = sqrt(-2.0 * log(a1));
+    double sn, cs;
+    sincospi(2.0 * a2, &sn, &cs);
+    z[2 * pr] = r * cs;
+    z[2 * pr + 1] = r * sn;
+  }
+  for (int d = 0; d < 5; ++d) {
+    y[d] = (double)mu[k * 5 + d] + (double)sg[k * 5 + d] * z[d];
+    u[d] = 1.0 / (1.0 + exp(-y[d]));
+  }
+}
+
+// log of u(1-u) from y = logit(u), written stably
+template <typename R>
+__device__ __forceinline__ R log_u1mu(R y) {
+  const R a = y < R(0) ? -y : y;
+  return -a - R(2) * log1p(exp(-a));
+}
+
+// q(u) in FP64 straight from the table row (reference-precision path)
+__device__ __forceinline__ double mix_density_f64(const uint32_t* thr, const float* mu, const float* sg, int K,
+                                                  const double y[5]) {
+  double lk[16];
+  double mx = -1e300;
+  for (int k = 0; k < K; ++k) {
+    const double hi = k + 1 < K ? (double)thr[k + 1] : kTwo32;
+    const double pk = (hi - (double)thr[k]) / kTwo32;
+    if (!(pk > 0.0)) { lk[k] = -1e300; continue; }
+    double l = log(pk);
+    for (int d = 0; d < 5; ++d) {
+      const double s = (double)sg[k * 5 + d];
+      const double z = (y[d] - (double)mu[k * 5 + d]) / s;
+      l += -0.5 * z * z - log(s) - kHalfLog2Pi;
+    }
+    lk[k] = l;
+    mx = fmax(mx, l);
+  }
+  double acc = 0.0;
+  for (int k = 0; k < K; ++k) acc += exp(lk[k] - mx);
+  double lq = mx + log(acc);
+  for (int d = 0; d < 5; ++d) lq -= log_u1mu<double>(y[d]);
+  return (double)thr[0] / kTwo32 + exp(lq);
+}
+
+// Per-item constants of the FP32 density: mu (40), 1/sigma (40), log pi_k -
+// sum_d log sigma_kd - 5/2 log 2 pi (8), alpha.
+constexpr int kMixRow = 90;
+
+__device__ __forceinline__ void mix_prepare_f32(const uint32_t* thr, const float* mu, const float* sg, int K,
+                                                float* row, int lane) {
+  for (int i = lane; i < K * 5; i += kWave) {
+    row[i] = mu[i];
+    row[40 + i] = 1.0f / sg[i];
+  }
+  if (lane < K) {
+    const double hi = lane + 1 < K ? (double)thr[lane + 1] : kTwo32;
+    const double pk = (hi - (double)thr[lane]) / kTwo32;
+    double c = pk > 0.0 ? log(pk) - 5.0 * kHalfLog2Pi : -1e30;
+    for (int d = 0; d < 5; ++d) c -= log((double)sg[lane * 5 + d]);
+    row[80 + lane] = (float)c;
+  }
+  if (lane == 0) row[88] = (float)((double)thr[0] / kTwo32);
+}
+
+__device__ __forceinline__ float mix_density_f32(const float* row, int K, const double y[5]) {
+  float yf[5];
+  for (int d = 0; d < 5; ++d) yf[d] = (float)y[d];
+  float lk[16];
+  float mx = -1e30f;
+  for (int k = 0; k < K; ++k) {
+    float l = row[80 + k];
+    for (int d = 0; d < 5; ++d) {
+      const float z = (yf[d] - row[k * 5 + d]) * row[40 + k * 5 + d];
+      l = fmaf(-0.5f * z, z, l);
+    }
+    lk[k] = l;
+    mx = fmaxf(mx, l);
+  }
+  float acc = 0.f;
+  for (int k = 0; k < K; ++k) acc += __expf(lk[k] - mx);
+  float lq = mx + __logf(acc);
+  for (int d = 0; d < 5; ++d) lq -= log_u1mu<float>(yf[d]);
+  return row[88] + __expf(lq);
+}
+
 // Set up the wave-uniform item constants.
 __device__ __forceinline__ void load_item(Item& it, const CollideArgs& A, const Channel& ch, int cell, int p1_lin) {
   const Grid& G = A.G;
@@ -257,6 +370,7 @@ __device__ __forceinline__ bool is_gluon(int sp) { return sp == kGluon; }
 // FP64 kernel: f read from the FP64 field in global memory, deposits as FP64
 // atomics into the output.  This is the reference-precision path.
 // ---------------------------------------------------------------------------
+template <bool kLearned>
 __global__ __launch_bounds__(256) void collide_f64_kernel(CollideArgs A) {
   const Grid& G = A.G;
   const int lane = threadIdx.x & (kWave - 1);
@@ -288,15 +402,29 @@ __global__ __launch_bounds__(256) void collide_f64_kernel(CollideArgs A) {
     const double F1 = g1 ? 1.0 + it.f1 : 1.0 - it.f1;
     double dsum = 0.0, ssum = 0.0;
     int n_ok = 0;
+    const size_t mrow = (size_t)ci * G.nodes + p1_lin;
     for (int s = lane; s < A.n_samples; s += kWave) {
       uint32_t x0 = (uint32_t)s, x1 = (uint32_t)p1_lin, x2 = (uint32_t)cell, x3 = ((uint32_t)ch.code << 8);
       philox4x32_10(x0, x1, x2, x3, A.key0, A.key1);
       double u[5];
-      five_uniforms(x0, x1, x2, x3, u);
+      double inv_q = 1.0;
+      if (kLearned) {
+        uint32_t y0 = (uint32_t)s, y1 = (uint32_t)p1_lin, y2 = (uint32_t)cell, y3 = ((uint32_t)ch.code << 8) | 1u;
+        philox4x32_10(y0, y1, y2, y3, A.key0, A.key1);
+        const uint32_t xw[8] = {x0, x1, x2, x3, y0, y1, y2, y3};
+        double yl[5];
+        const uint32_t* thr = A.mix_thr + mrow * A.mix_K;
+        const float* mu = A.mix_mu + mrow * A.mix_K * 5;
+        const float* sg = A.mix_sigma + mrow * A.mix_K * 5;
+        mix_draw(xw, thr, mu, sg, A.mix_K, u, yl);
+        inv_q = 1.0 / mix_density_f64(thr, mu, sg, A.mix_K, yl);
+      } else {
+        five_uniforms(x0, x1, x2, x3, u);
+      }
       Geo g;
       if (!geometry(it, G, u, g)) continue;
       ++n_ok;
-      const double wnb = weight_no_bracket<double>(it, g, ch.row, G.g4);
+      const double wnb = weight_no_bracket<double>(it, g, ch.row, G.g4) * inv_q;
       const Stencil<double> s2 = make_stencil<double>(g.p2, G);
       const Stencil<double> s3 = make_stencil<double>(g.p3, G);
       const Stencil<double> s4 = make_stencil<double>(g.p4, G);
@@ -361,9 +489,10 @@ __device__ __forceinline__ void deposit_slot(int k, int n_acc, double* acc, doub
   else deposit<double, double>(out + goff[k], widen(st), (double)v, ox, oy);
 }
 
-template <bool kSym, bool kScale, bool kTilesLds>
+template <bool kSym, bool kScale, bool kTilesLds, bool kLearned>
 __global__ __launch_bounds__(512) void collide_f32_kernel(CollideArgs A) {
   extern __shared__ double lds[];
+  __shared__ float mix_rows[kLearned ? 8 : 1][kLearned ? kMixRow : 1];
   const Grid& G = A.G;
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
@@ -404,15 +533,34 @@ __global__ __launch_bounds__(512) void collide_f32_kernel(CollideArgs A) {
     const float F1 = g1 ? 1.0f + f1 : 1.0f - f1;
     double dsum = 0.0, ssum = 0.0;
     int n_ok = 0;
+    const size_t mrow = (size_t)ci * nodes + p1_lin;
+    if (kLearned) {
+      mix_prepare_f32(A.mix_thr + mrow * A.mix_K, A.mix_mu + mrow * A.mix_K * 5, A.mix_sigma + mrow * A.mix_K * 5,
+                      A.mix_K, mix_rows[wid], lane);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
     for (int s = lane; s < A.n_samples; s += kWave) {
       uint32_t x0 = (uint32_t)s, x1 = (uint32_t)p1_lin, x2 = (uint32_t)cell, x3 = ((uint32_t)ch.code << 8);
       philox4x32_10(x0, x1, x2, x3, A.key0, A.key1);
       double u[5];
-      five_uniforms(x0, x1, x2, x3, u);
+      float inv_q = 1.0f;
+      if (kLearned) {
+        uint32_t y0 = (uint32_t)s, y1 = (uint32_t)p1_lin, y2 = (uint32_t)cell, y3 = ((uint32_t)ch.code << 8) | 1u;
+        philox4x32_10(y0, y1, y2, y3, A.key0, A.key1);
+        const uint32_t xw[8] = {x0, x1, x2, x3, y0, y1, y2, y3};
+        double yl[5];
+        mix_draw(xw, A.mix_thr + mrow * A.mix_K, A.mix_mu + mrow * A.mix_K * 5, A.mix_sigma + mrow * A.mix_K * 5,
+                 A.mix_K, u, yl);
+        inv_q = 1.0f / mix_density_f32(mix_rows[wid], A.mix_K, yl);
+      } else {
+        five_uniforms(x0, x1, x2, x3, u);
+      }
       Geo g;
       if (!geometry(it, G, u, g)) continue;
       ++n_ok;
-      const float wnb = weight_no_bracket<float>(it, g, ch.row, G.g4);
+      const float wnb = weight_no_bracket<float>(it, g, ch.row, G.g4) * inv_q;
       const Stencil<float> s2 = make_stencil<float>(g.p2, G);
       const Stencil<float> s3 = make_stencil<float>(g.p3, G);
       const Stencil<float> s4 = make_stencil<float>(g.p4, G);
@@ -461,6 +609,75 @@ __global__ __launch_bounds__(512) void collide_f32_kernel(CollideArgs A) {
 }
 
 // ---------------------------------------------------------------------------
+// Training data for the proposal: for every item_stride-th work item
+// (cell, channel, node; node fastest), n_per_item uniform samples are drawn
+// exactly as the uniform sampler draws them and recorded as rows
+// [x (8 features), y = logit(u) (5), |value|].  FP64 evaluation.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void record_kernel(CollideArgs A, int n_per_item, long long item_stride,
+                                                     long long n_sel, float* __restrict__ rows) {
+  const Grid& G = A.G;
+  const long long total = n_sel * n_per_item;
+  const double pn = sqrt(G.ph[0] * G.ph[0] + G.ph[1] * G.ph[1] + G.ph[2] * G.ph[2]);
+  for (long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x; r < total;
+       r += (long long)gridDim.x * blockDim.x) {
+    const long long j = r / n_per_item;
+    const int s = (int)(r % n_per_item);
+    const long long w = j * item_stride;
+    const int p1_lin = (int)(w % G.nodes);
+    const int ci = (int)((w / G.nodes) % A.n_channels);
+    const int cell = (int)(w / ((long long)G.nodes * A.n_channels));
+    const Channel ch = A.chans[ci];
+    Item it;
+    load_item(it, A, ch, cell, p1_lin);
+    float* out = rows + (size_t)r * 14;
+    const double a = sqrt(it.p1[0] * it.p1[0] + it.p1[1] * it.p1[1] + it.p1[2] * it.p1[2]);
+    out[0] = (float)(it.p1[0] / G.ph[0]);
+    out[1] = (float)(it.p1[1] / G.ph[1]);
+    out[2] = (float)(it.p1[2] / G.ph[2]);
+    out[3] = (float)(a / pn);
+    out[4] = (float)(it.E1 / pn);
+    out[5] = (float)(it.mu / (pn * pn));
+    out[6] = (float)(ch.sp[0] / 3.0 - 1.0);
+    out[7] = A.n_channels > 1 ? (float)(2.0 * ci / (A.n_channels - 1) - 1.0) : 0.0f;
+    uint32_t x0 = (uint32_t)s, x1 = (uint32_t)p1_lin, x2 = (uint32_t)cell, x3 = ((uint32_t)ch.code << 8);
+    philox4x32_10(x0, x1, x2, x3, A.key0, A.key1);
+    double u[5];
+    five_uniforms(x0, x1, x2, x3, u);
+    for (int d = 0; d < 5; ++d) out[8 + d] = (float)log(u[d] / (1.0 - u[d]));
+    double v = 0.0;
+    Geo g;
+    if (it.E1 > 0.0 && geometry(it, G, u, g)) {
+      const double wnb = weight_no_bracket<double>(it, g, ch.row, G.g4);
+      const Stencil<double> s2 = make_stencil<double>(g.p2, G);
+      const Stencil<double> s3 = make_stencil<double>(g.p3, G);
+      const Stencil<double> s4 = make_stencil<double>(g.p4, G);
+      const double* f = A.f64;
+      const double f2 = interpolate<double>(f + ((size_t)ch.sp[1] * G.cells + cell) * G.nodes, s2, G.ox, G.oy);
+      const double f3 = interpolate<double>(f + ((size_t)ch.sp[2] * G.cells + cell) * G.nodes, s3, G.ox, G.oy);
+      const double f4 = interpolate<double>(f + ((size_t)ch.sp[3] * G.cells + cell) * G.nodes, s4, G.ox, G.oy);
+      const double F1 = is_gluon(ch.sp[0]) ? 1.0 + it.f1 : 1.0 - it.f1;
+      const double F2 = is_gluon(ch.sp[1]) ? 1.0 + f2 : 1.0 - f2;
+      const double F3 = is_gluon(ch.sp[2]) ? 1.0 + f3 : 1.0 - f3;
+      const double F4 = is_gluon(ch.sp[3]) ? 1.0 + f4 : 1.0 - f4;
+      v = wnb * (f3 * f4 * F1 * F2 - it.f1 * f2 * F3 * F4);
+    }
+    out[13] = (float)fabs(v);
+  }
+}
+
+hipError_t launch_record(const CollideArgs& a, int n_per_item, long long item_stride, long long n_sel, float* rows,
+                         hipStream_t stream) {
+  const long long total = n_sel * n_per_item;
+  long long blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(record_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, a, n_per_item, item_stride, n_sel,
+                     rows);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 hipError_t launch_collide_f64(const CollideArgs& a, hipStream_t stream) {
@@ -469,16 +686,25 @@ hipError_t launch_collide_f64(const CollideArgs& a, hipStream_t stream) {
   long long blocks = (items * kWave + threads - 1) / threads;
   if (blocks > 65536) blocks = 65536;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(collide_f64_kernel, dim3((unsigned)blocks), dim3(threads), 0, stream, a);
+  if (a.learned)
+    hipLaunchKernelGGL(collide_f64_kernel<true>, dim3((unsigned)blocks), dim3(threads), 0, stream, a);
+  else
+    hipLaunchKernelGGL(collide_f64_kernel<false>, dim3((unsigned)blocks), dim3(threads), 0, stream, a);
   return hipGetLastError();
 }
 
-template <bool kSym, bool kScale>
+template <bool kSym, bool kScale, bool kLearned>
 void launch_f32_variant(const CollideArgs& a, bool tiles_lds, dim3 grid, dim3 block, size_t lds, hipStream_t st) {
   if (tiles_lds)
-    hipLaunchKernelGGL((collide_f32_kernel<kSym, kScale, true>), grid, block, lds, st, a);
+    hipLaunchKernelGGL((collide_f32_kernel<kSym, kScale, true, kLearned>), grid, block, lds, st, a);
   else
-    hipLaunchKernelGGL((collide_f32_kernel<kSym, kScale, false>), grid, block, lds, st, a);
+    hipLaunchKernelGGL((collide_f32_kernel<kSym, kScale, false, kLearned>), grid, block, lds, st, a);
+}
+
+template <bool kSym, bool kScale>
+void launch_f32_sampler(const CollideArgs& a, bool tiles_lds, dim3 grid, dim3 block, size_t lds, hipStream_t st) {
+  if (a.learned) launch_f32_variant<kSym, kScale, true>(a, tiles_lds, grid, block, lds, st);
+  else launch_f32_variant<kSym, kScale, false>(a, tiles_lds, grid, block, lds, st);
 }
 
 hipError_t launch_collide_f32(const CollideArgs& a, int nslot, hipStream_t stream) {
@@ -491,11 +717,11 @@ hipError_t launch_collide_f32(const CollideArgs& a, int nslot, hipStream_t strea
   if (blocks <= 0) return hipSuccess;
   const dim3 grid((unsigned)blocks), block(threads);
   if (a.symmetric) {
-    if (a.scale) launch_f32_variant<true, true>(a, tiles_lds, grid, block, lds, stream);
-    else launch_f32_variant<true, false>(a, tiles_lds, grid, block, lds, stream);
+    if (a.scale) launch_f32_sampler<true, true>(a, tiles_lds, grid, block, lds, stream);
+    else launch_f32_sampler<true, false>(a, tiles_lds, grid, block, lds, stream);
   } else {
-    if (a.scale) launch_f32_variant<false, true>(a, tiles_lds, grid, block, lds, stream);
-    else launch_f32_variant<false, false>(a, tiles_lds, grid, block, lds, stream);
+    if (a.scale) launch_f32_sampler<false, true>(a, tiles_lds, grid, block, lds, stream);
+    else launch_f32_sampler<false, false>(a, tiles_lds, grid, block, lds, stream);
   }
   return hipGetLastError();
 }
@@ -504,14 +730,15 @@ hipError_t set_collide_lds_limit(size_t bytes) {
   // Raising the per-kernel dynamic LDS limit is only needed (and only
   // accepted) above the runtime's default; a refusal leaves the default, which
   // the planner's budget then has to respect, so it is not an error here.
-  const void* fns[8] = {(const void*)collide_f32_kernel<true, true, true>,
-                        (const void*)collide_f32_kernel<true, false, true>,
-                        (const void*)collide_f32_kernel<false, true, true>,
-                        (const void*)collide_f32_kernel<false, false, true>,
-                        (const void*)collide_f32_kernel<true, true, false>,
-                        (const void*)collide_f32_kernel<true, false, false>,
-                        (const void*)collide_f32_kernel<false, true, false>,
-                        (const void*)collide_f32_kernel<false, false, false>};
+  const void* fns[16] = {
+      (const void*)collide_f32_kernel<true, true, true, false>,   (const void*)collide_f32_kernel<true, false, true, false>,
+      (const void*)collide_f32_kernel<false, true, true, false>,  (const void*)collide_f32_kernel<false, false, true, false>,
+      (const void*)collide_f32_kernel<true, true, false, false>,  (const void*)collide_f32_kernel<true, false, false, false>,
+      (const void*)collide_f32_kernel<false, true, false, false>, (const void*)collide_f32_kernel<false, false, false, false>,
+      (const void*)collide_f32_kernel<true, true, true, true>,    (const void*)collide_f32_kernel<true, false, true, true>,
+      (const void*)collide_f32_kernel<false, true, true, true>,   (const void*)collide_f32_kernel<false, false, true, true>,
+      (const void*)collide_f32_kernel<true, true, false, true>,   (const void*)collide_f32_kernel<true, false, false, true>,
+      (const void*)collide_f32_kernel<false, true, false, true>,  (const void*)collide_f32_kernel<false, false, false, true>};
   for (const void* fn : fns) {
     hipFuncAttributes attr;
     if (hipFuncGetAttributes(&attr, fn) != hipSuccess) return hipGetLastError();

@@ -1,0 +1,103 @@
+// Context of libqgbe shared by the host-side translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "collide.h"
+#include "field.h"
+#include "mlp.h"
+#include "qgbe.h"
+#include "qgbe_common.h"
+
+namespace qgbe {
+
+qgbe_status fail(qgbe_status s, const std::string& msg);
+qgbe_status hip_fail(hipError_t e, const char* what);
+
+#define HIP_TRY(expr, what)                                \
+  do {                                                     \
+    hipError_t _e = (expr);                                \
+    if (_e != hipSuccess) return ::qgbe::hip_fail(_e, what); \
+  } while (0)
+
+// LDS kept free for the collision kernel's static arrays
+constexpr size_t kStaticLds = 3072;
+
+// Channels of the FP32 kernel grouped by their number of deposit slots.
+struct Group {
+  int start, count;   // range in the group index array
+  int nslot;          // distinct species at positions 2..4
+  int lds_acc;        // FP64 accumulators staged in LDS
+  int lds_tiles;      // FP32 f tiles staged in LDS
+};
+
+// Device buffers of the proposal network (allocated on first use).
+struct MlpState {
+  bool ready = false;
+  bool has_weights = false;
+  int adam_t = 0;
+  float *params = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
+  __bf16* pb = nullptr;
+  float *X = nullptr, *Z1 = nullptr, *Z2 = nullptr, *Y = nullptr, *dY = nullptr, *dH = nullptr, *dZ = nullptr;
+  float* yw = nullptr;
+  __bf16 *Xb = nullptr, *H1b = nullptr, *H2b = nullptr, *dYb = nullptr, *dZb = nullptr;
+  double* scalars = nullptr;   // [0] loss, [1] weight sum
+  int* idx = nullptr;
+};
+
+}  // namespace qgbe
+
+struct qgbe_ctx {
+  qgbe_grid_desc d{};
+  qgbe::Grid G{};
+  hipStream_t stream = nullptr;
+  int nch = 0;
+  std::vector<qgbe::Channel> chans;
+  std::vector<int> group_index;
+  std::vector<qgbe::Group> groups;
+  qgbe::Channel* d_chans = nullptr;
+  int* d_groups = nullptr;
+  int* d_all = nullptr;            // identity channel list (FP64 kernel)
+  double* d_f = nullptr;
+  double* d_f_next = nullptr;
+  float* d_f32 = nullptr;
+  double* d_mass2 = nullptr;
+  double* d_lag = nullptr;
+  bool has_lag = false;
+  bool masses_valid = false;       // d_mass2 holds the masses of the current f
+  double* d_A = nullptr;
+  double* d_obs_scratch = nullptr;
+  double* d_obs = nullptr;
+  unsigned long long* d_count = nullptr;
+  uint32_t step = 0;
+  int K = 0;                       // proposal table components (0 = none)
+  uint32_t* d_thr = nullptr;
+  float* d_mu = nullptr;
+  float* d_sigma = nullptr;
+  qgbe::MlpState mlp;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  size_t ws = 0;
+  size_t lds_bytes = 0;            // dynamic LDS available per workgroup
+};
+
+namespace qgbe {
+
+size_t field_len(const qgbe_ctx* c);
+qgbe_status compute_masses(qgbe_ctx* c);
+CollideArgs base_args(qgbe_ctx* c, int n_samples, double* A, double* scale, double* items);
+
+template <typename T>
+qgbe_status dev_alloc(qgbe_ctx* c, T** p, size_t n, const char* what) {
+  hipError_t e = hipMalloc((void**)p, n * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return hip_fail(e, what);
+  }
+  c->ws += n * sizeof(T);
+  return QGBE_OK;
+}
+
+}  // namespace qgbe

@@ -28,8 +28,13 @@ EXPORTS = (
     "qgbe_set_distribution", "qgbe_get_distribution", "qgbe_get_masses",
     "qgbe_set_step_index", "qgbe_get_step_index", "qgbe_collision_term",
     "qgbe_collision_term_ex", "qgbe_step", "qgbe_observables", "qgbe_set_proposal_table",
-    "qgbe_channel_table", "qgbe_philox4x32_10",
+    "qgbe_channel_table", "qgbe_philox4x32_10", "qgbe_proposal_set_weights",
+    "qgbe_proposal_get_weights", "qgbe_mlp_forward", "qgbe_mlp_loss_grad", "qgbe_proposal_features",
+    "qgbe_record_samples", "qgbe_train_proposal", "qgbe_proposal_build_table", "qgbe_get_proposal_table",
 )
+MLP_PARAMS = 29016
+MLP_BATCH = 16384
+RECORD_WIDTH = 14
 
 
 class QgbeError(RuntimeError):
@@ -60,6 +65,11 @@ class Stats(C.Structure):
             v = getattr(self, name)
             out[name] = list(v) if hasattr(v, "__len__") else v
         return out
+
+
+class TrainCfg(C.Structure):
+    _fields_ = [("epochs", C.c_int32), ("batch", C.c_int32), ("lr", C.c_float), ("lr_final", C.c_float),
+                ("alpha", C.c_float), ("seed", C.c_uint64)]
 
 
 class CollideExtras(C.Structure):
@@ -94,6 +104,15 @@ def lib() -> C.CDLL:
             "qgbe_set_proposal_table": (i32, [p, i32, p, p, p, i32]),
             "qgbe_channel_table": (i32, [u32, u32, p, p, i32]),
             "qgbe_philox4x32_10": (None, [p, p, p]),
+            "qgbe_proposal_set_weights": (i32, [p, p, C.c_int64]),
+            "qgbe_proposal_get_weights": (i32, [p, p, C.c_int64]),
+            "qgbe_mlp_forward": (i32, [p, p, C.c_int64, p, i32]),
+            "qgbe_mlp_loss_grad": (i32, [p, p, p, C.c_int64, p, p, i32]),
+            "qgbe_proposal_features": (i32, [p, p, i32]),
+            "qgbe_record_samples": (i32, [p, i32, C.c_int64, p, C.c_int64, p, i32]),
+            "qgbe_train_proposal": (i32, [p, p, C.c_int64, p, p, i32]),
+            "qgbe_proposal_build_table": (i32, [p, C.c_float]),
+            "qgbe_get_proposal_table": (i32, [p, p, p, p, p]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -227,6 +246,72 @@ def qgbe_set_proposal_table(ctx, thr, mu, sigma) -> None:
         raise ValueError("table arrays must all be host or all device buffers")
     K = int(thr.shape[-1])
     _check(lib().qgbe_set_proposal_table(ctx, K, tp, mp, sp, d1))
+
+
+def qgbe_proposal_set_weights(ctx, w: np.ndarray) -> None:
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    _check(lib().qgbe_proposal_set_weights(ctx, w.ctypes.data_as(C.c_void_p), w.size))
+
+
+def qgbe_proposal_get_weights(ctx) -> np.ndarray:
+    w = np.zeros(MLP_PARAMS, dtype=np.float32)
+    _check(lib().qgbe_proposal_get_weights(ctx, w.ctypes.data_as(C.c_void_p), w.size))
+    return w
+
+
+def qgbe_mlp_forward(ctx, X, Y) -> None:
+    xp, d1 = _arg(X, np.float32)
+    yp, d2 = _arg(Y, np.float32)
+    if d1 != d2:
+        raise ValueError("X and Y must both be host or both device buffers")
+    rows = X.shape[0]
+    _check(lib().qgbe_mlp_forward(ctx, xp, rows, yp, d1))
+
+
+def qgbe_mlp_loss_grad(ctx, X, yw, grad) -> float:
+    xp, d1 = _arg(X, np.float32)
+    wp, d2 = _arg(yw, np.float32)
+    gp, d3 = _arg(grad, np.float32)
+    if not d1 == d2 == d3:
+        raise ValueError("buffers must all be host or all device")
+    loss = C.c_double()
+    _check(lib().qgbe_mlp_loss_grad(ctx, xp, wp, X.shape[0], gp, C.byref(loss), d1))
+    return loss.value
+
+
+def qgbe_proposal_features(ctx, X) -> None:
+    xp, dev = _arg(X, np.float32)
+    _check(lib().qgbe_proposal_features(ctx, xp, dev))
+
+
+def qgbe_record_samples(ctx, n_per_item: int, item_stride: int, rows) -> int:
+    rp, dev = _arg(rows, np.float32)
+    n = C.c_int64()
+    max_rows = (rows.numel() if hasattr(rows, "numel") else rows.size) // RECORD_WIDTH
+    _check(lib().qgbe_record_samples(ctx, n_per_item, item_stride, rp, max_rows, C.byref(n), dev))
+    return n.value
+
+
+def qgbe_train_proposal(ctx, rows, cfg: TrainCfg, epoch_loss: np.ndarray | None = None) -> None:
+    rp, dev = _arg(rows, np.float32)
+    n = (rows.numel() if hasattr(rows, "numel") else rows.size) // RECORD_WIDTH
+    lp = None if epoch_loss is None else epoch_loss.ctypes.data_as(C.c_void_p)
+    _check(lib().qgbe_train_proposal(ctx, rp, n, C.byref(cfg), lp, dev))
+
+
+def qgbe_proposal_build_table(ctx, alpha: float = 0.1) -> None:
+    _check(lib().qgbe_proposal_build_table(ctx, alpha))
+
+
+def qgbe_get_proposal_table(ctx, rows: int):
+    K = C.c_int32()
+    _check(lib().qgbe_get_proposal_table(ctx, C.byref(K), None, None, None))
+    thr = np.zeros((rows, K.value), dtype=np.uint32)
+    mu = np.zeros((rows, K.value, 5), dtype=np.float32)
+    sg = np.zeros((rows, K.value, 5), dtype=np.float32)
+    _check(lib().qgbe_get_proposal_table(ctx, C.byref(K), thr.ctypes.data_as(C.c_void_p),
+                                         mu.ctypes.data_as(C.c_void_p), sg.ctypes.data_as(C.c_void_p)))
+    return thr, mu, sg
 
 
 def qgbe_channel_table(species_mask: int, row_mask: int = 0x7F):

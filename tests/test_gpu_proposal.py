@@ -1,0 +1,178 @@
+"""GPU tests of the learned proposal against the FP64 oracle.
+
+* network forward and loss/gradient: the GPU multiplies BF16 operands with
+  FP32 accumulation; the oracle evaluates the same network in FP64 with the
+  same operands rounded to BF16.  Bar: relative L2 <= 1e-2 per tensor.
+* conditioning features: FP32 of the same FP64 values (rtol 1e-6).
+* learned-sampler collision term with a seeded random mixture table (input to
+  both sides): FP64 mode within 1e-10 of the cell scale, FP32 within 1e-4.
+* after training on the solver's own samples, the learned estimator agrees
+  with the uniform one in expectation and has lower MC error at equal N.
+"""
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+from paper_1912_04457_amd import qgbe
+from paper_1912_04457_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SEED = 0x5EED2019
+
+
+def _case(name):
+    print(f"\n[gpu case] {name}", flush=True)
+
+
+def _rel(a, b):
+    return np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300)
+
+
+SMALL_7 = W.Workload("qg7_2cells_5x6x4", (2, 1, 1), (5, 6, 4), (3.0, 3.0, 3.0), (2.0, 2.5, 1.5),
+                     0x7F, 100, "f64", 1, 0.01)
+
+
+def _kw(wl):
+    return dict(n_x=wl.n_x, n_p=wl.n_p, x_half=wl.x_half, p_half=wl.p_half,
+                species_mask=wl.species_mask, alpha_s=wl.alpha_s, seed=SEED)
+
+
+def _mlp_inputs(rows, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    X = rng.uniform(-1, 1, (rows, M.N_IN)).astype(np.float32)
+    yw = np.concatenate([rng.normal(0, 1.5, (rows, M.D)), rng.uniform(0.1, 2.0, (rows, 1))], 1).astype(np.float32)
+    return X, yw
+
+
+def test_mlp_forward_matches_oracle():
+    _case("mlp forward")
+    w = W.random_mlp_params(3, head_scale=1.0)
+    X, _ = _mlp_inputs(1000, 4)
+    with qgbe.Solver(**_kw(SMALL_7)) as s:
+        qgbe.qgbe_proposal_set_weights(s.ctx, w)
+        Y = np.zeros((1000, M.N_OUT), dtype=np.float32)
+        qgbe.qgbe_mlp_forward(s.ctx, X, Y)
+        assert np.array_equal(qgbe.qgbe_proposal_get_weights(s.ctx), w)
+    Yref, _ = M.forward(M.unflatten(w.astype(np.float64)), X.astype(np.float64), quantize=M.bf16)
+    assert _rel(Y, Yref) <= 1e-2, _rel(Y, Yref)
+
+
+def test_mlp_loss_and_gradient_match_oracle():
+    _case("mlp loss/grad")
+    w = W.random_mlp_params(5, head_scale=1.0)
+    X, yw = _mlp_inputs(2000, 6)
+    with qgbe.Solver(**_kw(SMALL_7)) as s:
+        qgbe.qgbe_proposal_set_weights(s.ctx, w)
+        grad = np.zeros(qgbe.MLP_PARAMS, dtype=np.float32)
+        loss = qgbe.qgbe_mlp_loss_grad(s.ctx, X, yw, grad)
+    p = M.unflatten(w.astype(np.float64))
+    lref, gref = M.loss_and_grad(p, X.astype(np.float64), yw[:, :5].astype(np.float64),
+                                 yw[:, 5].astype(np.float64), quantize=M.bf16)
+    assert loss == pytest.approx(lref, rel=1e-3)
+    g = M.unflatten(grad.astype(np.float64))
+    for name, _ in M.PARAM_SHAPES:
+        assert _rel(g[name], gref[name]) <= 1e-2, (name, _rel(g[name], gref[name]))
+
+
+def test_features_match_oracle(O):
+    _case("features")
+    wl = SMALL_7
+    f = W.random_f(31, wl.cells, wl.nodes)
+    g = O.Grid(n_x=wl.n_x, n_p=wl.n_p, x_half=wl.x_half, p_half=wl.p_half, species_mask=wl.species_mask)
+    chans = O.channels(g)
+    with qgbe.Solver(**_kw(wl)) as s:
+        s.set_f(f)
+        X = np.zeros((len(chans) * wl.nodes, 8), dtype=np.float32)
+        qgbe.qgbe_proposal_features(s.ctx, X)
+    m = O.masses(g, f)
+    P = g.momenta()
+    ref = np.concatenate([M.features(P, m[c["sp"][0], 0], m[6, 0], c["sp"][0], i, len(chans), wl.p_half)
+                          for i, c in enumerate(chans)])
+    assert np.allclose(X, ref, rtol=1e-6, atol=1e-7)
+
+
+def test_table_from_network(O):
+    _case("table build")
+    wl = SMALL_7
+    f = W.random_f(32, wl.cells, wl.nodes)
+    w = W.random_mlp_params(7, head_scale=1.0)
+    g = O.Grid(n_x=wl.n_x, n_p=wl.n_p, x_half=wl.x_half, p_half=wl.p_half, species_mask=wl.species_mask)
+    chans = O.channels(g)
+    rows = len(chans) * wl.nodes
+    with qgbe.Solver(**_kw(wl)) as s:
+        s.set_f(f)
+        qgbe.qgbe_proposal_set_weights(s.ctx, w)
+        qgbe.qgbe_proposal_build_table(s.ctx, 0.1)
+        thr, mu, sg = qgbe.qgbe_get_proposal_table(s.ctx, rows)
+    m = O.masses(g, f)
+    X = np.concatenate([M.features(g.momenta(), m[c["sp"][0], 0], m[6, 0], c["sp"][0], i, len(chans), wl.p_half)
+                        for i, c in enumerate(chans)])
+    Y, _ = M.forward(M.unflatten(w.astype(np.float64)), X, quantize=M.bf16)
+    t_ref, mu_ref, sg_ref = M.table_from_head(Y, 0.1)
+    assert np.all(thr[:, 0] == t_ref[:, 0])
+    assert np.abs(thr.astype(np.float64) - t_ref).max() <= 2**32 * 2e-2
+    assert _rel(mu, mu_ref) <= 1e-2 and _rel(sg, sg_ref) <= 1e-2
+
+
+@pytest.mark.parametrize("precision,tol", [(qgbe.FP64, 1e-10), (qgbe.FP32, 1e-4)])
+def test_learned_collision_parity(O, precision, tol):
+    _case(f"learned collision parity precision={precision}")
+    wl = SMALL_7
+    f = W.random_f(33, wl.cells, wl.nodes)
+    g = O.Grid(n_x=wl.n_x, n_p=wl.n_p, x_half=wl.x_half, p_half=wl.p_half, species_mask=wl.species_mask)
+    rows = len(O.channels(g)) * wl.nodes
+    thr, mu, sg = W.random_mog_table(34, rows, K=8, alpha=0.1, mu_scale=1.0, log_sigma=(-1.0, 0.5))
+    with qgbe.Solver(**_kw(wl), precision=precision) as s:
+        s.set_f(f)
+        qgbe.qgbe_set_step_index(s.ctx, 2)
+        qgbe.qgbe_set_proposal_table(s.ctx, thr, mu, sg)
+        A, _, _, _ = s.collision(100, sampler=qgbe.SAMPLER_LEARNED)
+    m = O.masses(g, f)
+    A_ref, S_ref, _ = O.collision_learned(g, f, m, SEED, 2, 100, thr, mu, sg)
+    err = np.abs(A - A_ref)
+    assert np.all(err <= tol * S_ref + 1e-300), float((err / np.maximum(S_ref, 1e-300)).max())
+    assert _rel(A, A_ref) <= tol
+    for cell in range(wl.cells):
+        assert abs(A[:, cell].sum()) <= 1e-13 * S_ref[:, cell].sum()
+
+
+def _mc_error(samples):
+    mean = samples.mean(0)
+    var = samples.var(0, ddof=1)
+    return np.sqrt(var.mean()) / np.sqrt((mean ** 2).mean())
+
+
+def test_trained_proposal_unbiased_and_better():
+    """7 species, 8^3 momenta, CGC gluons + Fermi-Dirac quarks: train on the
+    solver's own uniform samples, then compare estimators at equal N."""
+    _case("train + compare")
+    wl = W.C3.scaled(n_p=(8, 8, 8))
+    f = W.initial_f(wl)
+    N, R = 64, 8
+    with qgbe.Solver(**_kw(wl), precision=qgbe.FP32) as s:
+        s.set_f(f)
+        rows = np.zeros((70 * wl.nodes * 16, qgbe.RECORD_WIDTH), dtype=np.float32)
+        n = qgbe.qgbe_record_samples(s.ctx, 16, 1, rows)
+        assert n == rows.shape[0]
+        assert np.isfinite(rows).all() and (rows[:, 13] > 0).mean() > 0.05
+        qgbe.qgbe_proposal_set_weights(s.ctx, W.random_mlp_params(11))
+        cfg = qgbe.TrainCfg(epochs=4, batch=4096, lr=2e-3, lr_final=2e-4, alpha=0.1, seed=1)
+        losses = np.zeros(4)
+        qgbe.qgbe_train_proposal(s.ctx, rows, cfg, losses)
+        print(f"[train] epoch losses {losses}", flush=True)
+        assert losses[-1] < losses[0]
+        plain, learned = [], []
+        for r in range(R):
+            qgbe.qgbe_set_step_index(s.ctx, 100 + r)
+            plain.append(s.collision(N)[0])
+            learned.append(s.collision(N, sampler=qgbe.SAMPLER_LEARNED)[0])
+    plain, learned = np.array(plain), np.array(learned)
+    e_plain, e_learned = _mc_error(plain), _mc_error(learned)
+    print(f"[train] MC error plain {e_plain:.4f} learned {e_learned:.4f}", flush=True)
+    assert e_learned < e_plain
+    diff = learned.mean(0) - plain.mean(0)
+    se = np.sqrt(learned.var(0, ddof=1) / R + plain.var(0, ddof=1) / R)
+    keep = se > 0
+    z = diff[keep] / se[keep]
+    assert np.mean(z ** 2) < 1.8 and np.abs(z).max() < 6.0, (np.mean(z ** 2), np.abs(z).max())

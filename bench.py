@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--samples", type=int, default=0, help="override samples per point")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="run one device copy of this many MiB before timing (counter calibration)")
     return ap.parse_args()
 
 
@@ -92,6 +94,14 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     import torch
+    if a.copy_mib:
+        # a plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE counters
+        # calibrate the byte counts read for the collision kernel
+        src = torch.ones(a.copy_mib * 2**18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     wl = W.WORKLOADS[a.workload]
     N = a.samples or wl.n_samples
     f0 = W.initial_f(wl)

@@ -85,6 +85,13 @@ def lib() -> C.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"libqgbe.so not built ({LIB_PATH}); run __graft_entry__.build()")
+        # PyTorch ships its own HIP runtime with the same sonames; loading it
+        # first lets libqgbe bind to that one runtime instead of a second copy
+        # (two runtimes in one process leave the later one without devices).
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         i32, u32, p, d = C.c_int32, C.c_uint32, C.c_void_p, C.c_double
         sig = {

@@ -109,7 +109,7 @@ def test_table_from_network(O):
     X = np.concatenate([M.features(g.momenta(), m[c["sp"][0], 0], m[6, 0], c["sp"][0], i, len(chans), wl.p_half)
                         for i, c in enumerate(chans)])
     Y, _ = M.forward(M.unflatten(w.astype(np.float64)), X, quantize=M.bf16)
-    t_ref, mu_ref, sg_ref = M.table_from_head(Y, 0.1)
+    t_ref, mu_ref, sg_ref = M.table_from_head(Y, float(np.float32(0.1)))   # the ABI takes alpha as FP32
     assert np.all(thr[:, 0] == t_ref[:, 0])
     assert np.abs(thr.astype(np.float64) - t_ref).max() <= 2**32 * 2e-2
     assert _rel(mu, mu_ref) <= 1e-2 and _rel(sg, sg_ref) <= 1e-2

@@ -33,15 +33,46 @@ constexpr int kWave = 64;
 
 __device__ __forceinline__ double unif23(uint32_t v) { return ((double)v + 0.5) * (1.0 / 8388608.0); }
 
+// FP64 1/x and 1/sqrt(x) for finite x > 0: the hardware estimate (about 23
+// correct bits) refined by two Newton steps, which reaches the last bit
+// without the scaling and special-case handling of a general division or
+// square root.
+__device__ __forceinline__ double rcp64(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+__device__ __forceinline__ double rsqrt64(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  double t = fma(-h * y, y, 0.5);
+  y = fma(y, t, y);
+  t = fma(-h * y, y, 0.5);
+  return fma(y, t, y);
+}
+
+// sqrt for x >= 0 (0 maps to 0)
+__device__ __forceinline__ double sqrt64(double x) { return x > 0.0 ? x * rsqrt64(x) : 0.0; }
+
+template <typename R>
+__device__ __forceinline__ R rcp_r(R x);
+template <>
+__device__ __forceinline__ float rcp_r<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <>
+__device__ __forceinline__ double rcp_r<double>(double x) { return rcp64(x); }
+
 // Table I |M|^2 in units of g^4, every t and u pole regulated by mu = m_g^2.
 // Group factors (SU(3), fundamental quarks): 8 dF^2 CF^2/dA = 16,
 // 16 dF CF (CF - CA/2) = -32/3, 8 dF CF^2 = 128/3, 8 dF CF CA = 96,
 // 16 dA CA^2 = 1152.
 template <typename R>
 __device__ __forceinline__ R matrix_element(int row, R s, R t, R u, R mu) {
-  const R rt = R(1) / (t - mu);
-  const R ru = R(1) / (u - mu);
-  const R rs = R(1) / s;
+  const R rt = rcp_r<R>(t - mu);
+  const R ru = rcp_r<R>(u - mu);
+  const R rs = rcp_r<R>(s);
   const R s2 = s * s, t2 = t * t, u2 = u * u;
   switch (row) {
     case 1: return R(16) * (s2 + u2) * rt * rt;
@@ -101,22 +132,28 @@ __device__ __forceinline__ R interpolate(const T* __restrict__ tile, const Stenc
 }
 
 // Scatter v with the stencil weights (the transpose of interpolate): values
-// in precision R, accumulators of type T.
-template <typename R, typename T>
+// in precision R, accumulators of type T.  kScope selects the atomic's memory
+// scope: workgroup for accumulators in LDS, agent for global memory (the two
+// kinds stay distinct instructions, so each keeps its address space).
+template <typename R, typename T, int kScope = __HIP_MEMORY_SCOPE_AGENT>
 __device__ __forceinline__ void deposit(T* acc, const Stencil<R>& st, R v, int ox, int oy) {
   T* q = acc + st.base;
   const R vx1 = v * st.wx, vx0 = v - vx1;
   const R v01 = vx0 * st.wy, v00 = vx0 - v01;
   const R v11 = vx1 * st.wy, v10 = vx1 - v11;
-  atomicAdd(q, (T)(v00 - v00 * st.wz));
-  atomicAdd(q + 1, (T)(v00 * st.wz));
-  atomicAdd(q + oy, (T)(v01 - v01 * st.wz));
-  atomicAdd(q + oy + 1, (T)(v01 * st.wz));
-  atomicAdd(q + ox, (T)(v10 - v10 * st.wz));
-  atomicAdd(q + ox + 1, (T)(v10 * st.wz));
-  atomicAdd(q + ox + oy, (T)(v11 - v11 * st.wz));
-  atomicAdd(q + ox + oy + 1, (T)(v11 * st.wz));
+  __hip_atomic_fetch_add(q, (T)(v00 - v00 * st.wz), __ATOMIC_RELAXED, kScope);
+  __hip_atomic_fetch_add(q + 1, (T)(v00 * st.wz), __ATOMIC_RELAXED, kScope);
+  __hip_atomic_fetch_add(q + oy, (T)(v01 - v01 * st.wz), __ATOMIC_RELAXED, kScope);
+  __hip_atomic_fetch_add(q + oy + 1, (T)(v01 * st.wz), __ATOMIC_RELAXED, kScope);
+  __hip_atomic_fetch_add(q + ox, (T)(v10 - v10 * st.wz), __ATOMIC_RELAXED, kScope);
+  __hip_atomic_fetch_add(q + ox + 1, (T)(v10 * st.wz), __ATOMIC_RELAXED, kScope);
+  __hip_atomic_fetch_add(q + ox + oy, (T)(v11 - v11 * st.wz), __ATOMIC_RELAXED, kScope);
+  __hip_atomic_fetch_add(q + ox + oy + 1, (T)(v11 * st.wz), __ATOMIC_RELAXED, kScope);
 }
+
+// 1 / ((2 pi)^3 * 2 * 2 * 16 pi^2): two-body phase space |p*|/(16 pi^2 sqrt s),
+// k2 measure d^3k2/((2 pi)^3 2 E2) and 1/(2 E1) of Eq. C_a_b
+constexpr double kNorm = 1.0 / (8.0 * kPi * kPi * kPi * 4.0 * 16.0 * kPi * kPi);
 
 // Quantities of a work item, identical for all lanes of the wave.
 struct Item {
@@ -129,6 +166,7 @@ struct Item {
   double mu;                // regulator m_g^2
   double f1;
   double coef;              // w V5 / N (symmetric) or sigma V5 / N (direct)
+  double pref;              // coef g^4 / ((2pi)^3 4 16 pi^2 E1): item part of the value
 };
 
 // The sampled configuration (FP64 geometry).
@@ -140,31 +178,31 @@ struct Geo {
 // Sample geometry from the five uniforms; false if below threshold or outside the box.
 __device__ __forceinline__ bool geometry(const Item& it, const Grid& G, const double u[5], Geo& g) {
   for (int a = 0; a < 3; ++a) g.p2[a] = fma(2.0 * G.ph[a], u[a], -G.ph[a]);
-  g.E2 = sqrt(g.p2[0] * g.p2[0] + g.p2[1] * g.p2[1] + g.p2[2] * g.p2[2] + it.m2sq);
+  g.E2 = sqrt64(g.p2[0] * g.p2[0] + g.p2[1] * g.p2[1] + g.p2[2] * g.p2[2] + it.m2sq);
   const double E = it.E1 + g.E2;
   const double P[3] = {it.p1[0] + g.p2[0], it.p1[1] + g.p2[1], it.p1[2] + g.p2[2]};
   const double s = E * E - (P[0] * P[0] + P[1] * P[1] + P[2] * P[2]);
   g.s = s;
   if (!(s > it.thr)) return false;
-  const double rs = 1.0 / sqrt(s);
+  const double rs = rsqrt64(s);
   const double sq = s * rs;
   g.rs = rs;
-  g.pstar = 0.5 * rs * sqrt((s - it.sum2) * (s - it.dif2));
+  g.pstar = 0.5 * rs * sqrt64((s - it.sum2) * (s - it.dif2));
   // k1 in the CM frame: p1* = p1 + P ((P.p1)/(sqrt s (E + sqrt s)) - E1/sqrt s)
-  const double inv_E = 1.0 / (E + sq);
+  const double inv_E = rcp64(E + sq);
   const double Pp1 = P[0] * it.p1[0] + P[1] * it.p1[1] + P[2] * it.p1[2];
   const double c1 = (Pp1 * inv_E - it.E1) * rs;
   double n[3] = {it.p1[0] + P[0] * c1, it.p1[1] + P[1] * c1, it.p1[2] + P[2] * c1};
-  const double rn = 1.0 / sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+  const double rn = rsqrt64(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
   n[0] *= rn; n[1] *= rn; n[2] *= rn;
   // orthonormal completion of n (Duff et al., JCGT 6(1), 2017)
   const double sgn = copysign(1.0, n[2]);
-  const double a = -1.0 / (sgn + n[2]);
+  const double a = -rcp64(sgn + n[2]);
   const double b = n[0] * n[1] * a;
   const double e1[3] = {1.0 + sgn * n[0] * n[0] * a, sgn * b, -sgn * n[0]};
   const double e2[3] = {b, sgn + n[1] * n[1] * a, -n[1]};
   const double cth = 2.0 * u[3] - 1.0;
-  const double sth = 2.0 * sqrt(u[3] * (1.0 - u[3]));
+  const double sth = 2.0 * sqrt64(u[3] * (1.0 - u[3]));
   double sphi, cphi;
   sincospi(2.0 * u[4], &sphi, &cphi);
   const double sc = sth * cphi, ss = sth * sphi;
@@ -348,17 +386,15 @@ __device__ __forceinline__ void load_item(Item& it, const CollideArgs& A, const 
   it.f1 = A.f64[((size_t)ch.sp[0] * G.cells + cell) * G.nodes + p1_lin];
   const double V5 = G.Vp * 4.0 * kPi;
   it.coef = (A.symmetric ? ch.w : ch.sigma) * V5 / (double)A.n_samples;
+  it.pref = it.coef * G.g4 * kNorm / it.E1;
 }
 
-// 1 / ((2 pi)^3 * 2 * 2 * 16 pi^2): two-body phase space |p*|/(16 pi^2 sqrt s),
-// k2 measure d^3k2/((2 pi)^3 2 E2) and 1/(2 E1) of Eq. C_a_b
-constexpr double kNorm = 1.0 / (8.0 * kPi * kPi * kPi * 4.0 * 16.0 * kPi * kPi);
 
 // Per-sample value (without the bracket) and the bracket, in precision R.
 template <typename R>
-__device__ __forceinline__ R weight_no_bracket(const Item& it, const Geo& g, int row, double g4) {
+__device__ __forceinline__ R weight_no_bracket(const Item& it, const Geo& g, int row) {
   const R m = matrix_element<R>(row, (R)g.s, (R)g.t, (R)g.u, (R)it.mu);
-  const R pre = (R)(it.coef * g4 * kNorm / it.E1) * (R)g.pstar * (R)g.rs / (R)g.E2;
+  const R pre = (R)it.pref * (R)g.pstar * (R)g.rs * rcp_r<R>((R)g.E2);
   return m * pre;
 }
 
@@ -424,7 +460,7 @@ __global__ __launch_bounds__(256) void collide_f64_kernel(CollideArgs A) {
       Geo g;
       if (!geometry(it, G, u, g)) continue;
       ++n_ok;
-      const double wnb = weight_no_bracket<double>(it, g, ch.row, G.g4) * inv_q;
+      const double wnb = weight_no_bracket<double>(it, g, ch.row) * inv_q;
       const Stencil<double> s2 = make_stencil<double>(g.p2, G);
       const Stencil<double> s3 = make_stencil<double>(g.p3, G);
       const Stencil<double> s4 = make_stencil<double>(g.p4, G);
@@ -485,7 +521,7 @@ __device__ __forceinline__ Stencil<double> widen(const Stencil<float>& st) {
 __device__ __forceinline__ void deposit_slot(int k, int n_acc, double* acc, double* __restrict__ out,
                                              const size_t* goff, const Stencil<float>& st, float v, int nodes,
                                              int ox, int oy) {
-  if (k < n_acc) deposit<double, double>(acc + k * nodes, widen(st), (double)v, ox, oy);
+  if (k < n_acc) deposit<double, double, __HIP_MEMORY_SCOPE_WORKGROUP>(acc + k * nodes, widen(st), (double)v, ox, oy);
   else deposit<double, double>(out + goff[k], widen(st), (double)v, ox, oy);
 }
 
@@ -560,7 +596,7 @@ __global__ __launch_bounds__(512) void collide_f32_kernel(CollideArgs A) {
       Geo g;
       if (!geometry(it, G, u, g)) continue;
       ++n_ok;
-      const float wnb = weight_no_bracket<float>(it, g, ch.row, G.g4) * inv_q;
+      const float wnb = weight_no_bracket<float>(it, g, ch.row) * inv_q;
       const Stencil<float> s2 = make_stencil<float>(g.p2, G);
       const Stencil<float> s3 = make_stencil<float>(g.p3, G);
       const Stencil<float> s4 = make_stencil<float>(g.p4, G);
@@ -648,7 +684,7 @@ __global__ __launch_bounds__(256) void record_kernel(CollideArgs A, int n_per_it
     double v = 0.0;
     Geo g;
     if (it.E1 > 0.0 && geometry(it, G, u, g)) {
-      const double wnb = weight_no_bracket<double>(it, g, ch.row, G.g4);
+      const double wnb = weight_no_bracket<double>(it, g, ch.row);
       const Stencil<double> s2 = make_stencil<double>(g.p2, G);
       const Stencil<double> s3 = make_stencil<double>(g.p3, G);
       const Stencil<double> s4 = make_stencil<double>(g.p4, G);

@@ -56,7 +56,104 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB before timing (counter calibration)")
+    ap.add_argument("--no-fixed-error", action="store_true",
+                    help="skip the plain-vs-learned time per step at fixed MC error")
+    ap.add_argument("--replicas", type=int, default=8)
     return ap.parse_args()
+
+
+def mc_error(reps):
+    """Relative MC error of replicated collision terms: sqrt(mean Var) / rms(mean)."""
+    reps = np.asarray(reps)
+    mean = reps.mean(0)
+    var = reps.var(0, ddof=1)
+    return float(np.sqrt(var.mean()) / np.sqrt((mean ** 2).mean()))
+
+
+def fixed_error(R):
+    """Time per step of the 7-species homogeneous workload (20^3 nodes, 70
+    channels) with the plain symmetric sampler at 4096 samples per point,
+    against the learned proposal at the smallest sample count whose MC error
+    is no larger.  The network is trained on the GPU on ~10^6 integrand
+    samples of the plain sampler; its time is reported separately.  The
+    learned step includes the network evaluation that rebuilds the proposal
+    table from the step's masses."""
+    wl = W.C3
+    n_plain = wl.n_samples
+    f0 = W.initial_f(wl)
+    out = {"workload": wl.name, "replicas": R, "samples_plain": n_plain}
+    solver = qgbe.Solver(n_x=wl.n_x, n_p=wl.n_p, x_half=wl.x_half, p_half=wl.p_half,
+                         species_mask=wl.species_mask, alpha_s=wl.alpha_s, precision=qgbe.FP32,
+                         drift=qgbe.DRIFT_UPWIND, seed=W.PHILOX_SEED, device=0)
+    with solver:
+        solver.set_f(f0)
+
+        def replicas(n, sampler):
+            reps = []
+            for r in range(R):
+                qgbe.qgbe_set_step_index(solver.ctx, 1000 + r)
+                reps.append(solver.collision(n, sampler=sampler)[0])
+            return reps
+
+        def step_ms(n, sampler, steps=5):
+            solver.set_f(f0)
+            qgbe.qgbe_set_step_index(solver.ctx, 0)
+            st = solver.step(wl.dt_fm, n, n_steps=steps + 1, sampler=sampler)
+            return float(np.median([s["t_step_ms"] for s in st[1:]])), float(
+                np.median([s["t_collide_ms"] for s in st[1:]]))
+
+        eps_plain = mc_error(replicas(n_plain, qgbe.SAMPLER_UNIFORM))
+        t_plain, c_plain = step_ms(n_plain, qgbe.SAMPLER_UNIFORM)
+        out.update(eps_plain=eps_plain, t_step_plain_ms=t_plain, t_collide_plain_ms=c_plain)
+
+        # training data: 2 uniform samples per (channel, node), ~1.1e6 rows
+        solver.set_f(f0)
+        items = wl.cells * solver.n_channels * wl.nodes
+        per_item = max(1, -(-1_000_000 // items))
+        import torch
+        rows = torch.empty((items * per_item, qgbe.RECORD_WIDTH), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n_rows = qgbe.qgbe_record_samples(solver.ctx, per_item, 1, rows)
+        qgbe.qgbe_proposal_set_weights(solver.ctx, W.random_mlp_params(1))
+        epochs = 6
+        cfg = qgbe.TrainCfg(epochs=epochs, batch=4096, lr=2e-3, lr_final=1e-4, alpha=0.1, seed=1)
+        losses = np.zeros(epochs)
+        qgbe.qgbe_train_proposal(solver.ctx, rows, cfg, losses)
+        torch.cuda.synchronize()
+        out.update(train_rows=n_rows, train_epochs=epochs, train_s=time.perf_counter() - t0,
+                   train_loss_first=float(losses[0]), train_loss_last=float(losses[-1]))
+        del rows
+
+        cache = {}
+
+        def eps_learned(n):
+            if n not in cache:
+                cache[n] = mc_error(replicas(n, qgbe.SAMPLER_LEARNED))
+            return cache[n]
+
+        # smallest power of two in [64, n_plain] reaching the plain error, then bisect
+        hi = 64
+        while hi < n_plain and eps_learned(hi) > eps_plain:
+            hi *= 2
+        if eps_learned(hi) > eps_plain:
+            out.update(samples_learned=None, eps_learned=eps_learned(hi),
+                       note="learned proposal did not reach the plain MC error at the plain sample count")
+            return out
+        lo = hi // 2 if hi > 64 else hi
+        while hi - lo > max(8, lo // 16):
+            mid = (lo + hi) // 2
+            if eps_learned(mid) <= eps_plain:
+                hi = mid
+            else:
+                lo = mid
+        n_learned = hi
+        t_learned, c_learned = step_ms(n_learned, qgbe.SAMPLER_LEARNED)
+        out.update(samples_learned=n_learned, eps_learned=eps_learned(n_learned),
+                   t_step_learned_ms=t_learned, t_collide_learned_ms=c_learned,
+                   time_ratio=t_plain / t_learned,
+                   bisection={str(k): v for k, v in sorted(cache.items())})
+    return out
 
 
 def cpu_baseline(wl, f, n_samples, budget_s):
@@ -147,6 +244,8 @@ def main():
         "collide_ms_per_step": float(t_coll.mean() * 1e3),
         "N_total_rel_drift": abs(stats[-1]["N_total"] - N0) / N0,
     }
+    if not a.no_fixed_error:
+        out["fixed_mc_error"] = fixed_error(a.replicas)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, f0, N, a.cpu_seconds)
     print(json.dumps(out))

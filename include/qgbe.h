@@ -239,8 +239,9 @@ qgbe_status qgbe_mlp_forward(qgbe_ctx* ctx, const float* X, int64_t rows, float*
 qgbe_status qgbe_mlp_loss_grad(qgbe_ctx* ctx, const float* X, const float* yw, int64_t rows, float* grad,
                                double* loss, int32_t on_device);
 
-/* Conditioning inputs of every (channel, node) row at cell 0 with the masses
- * of the last collision term or step: X [channels*nodes][8]. */
+/* Conditioning inputs of every (channel, node) row, built from the masses of
+ * the last collision term or step averaged over the cells (one table serves
+ * every cell): X [channels*nodes][8]. */
 qgbe_status qgbe_proposal_features(qgbe_ctx* ctx, float* X, int32_t on_device);
 
 /* Record training rows from uniform samples of the current f: for every
@@ -257,7 +258,10 @@ qgbe_status qgbe_train_proposal(qgbe_ctx* ctx, const float* rows, int64_t n, con
                                 double* epoch_loss, int32_t on_device);
 
 /* Evaluate the network on every (channel, node) row and install the result
- * as the proposal table (defensive share alpha). */
+ * as the proposal table (defensive share alpha).  From then on, every learned
+ * collision term or step re-evaluates the network on the current masses
+ * before sampling (the inference is part of that call's time), until
+ * qgbe_set_proposal_table installs a fixed table. */
 qgbe_status qgbe_proposal_build_table(qgbe_ctx* ctx, float alpha);
 
 /* Copy the installed proposal table out (thr [rows][K], mu, sigma

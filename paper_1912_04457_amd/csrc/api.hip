@@ -341,6 +341,8 @@ void qgbe_destroy(qgbe_ctx* c) {
   (void)hipFree(c->d_thr);
   (void)hipFree(c->d_mu);
   (void)hipFree(c->d_sigma);
+  (void)hipFree(c->d_feat);
+  (void)hipFree(c->d_mass7);
   {
     MlpState& m = c->mlp;
     void* bufs[] = {m.params, m.m, m.v, m.grad, m.pb, m.X, m.Xb, m.Z1, m.H1b, m.Z2, m.H2b, m.Y, m.dY, m.dYb,
@@ -424,6 +426,7 @@ qgbe_status qgbe_collision_term_ex(qgbe_ctx* c, int32_t n_samples, int32_t sampl
     else items = ex->item_sums;
   }
   qgbe_status s = compute_masses(c);
+  if (!s && sampler == QGBE_SAMPLER_LEARNED && c->table_net) s = refresh_proposal_table(c);
   if (!s) {
     hipError_t e = launch_fill(A, 0.0, n, c->stream);
     if (e == hipSuccess && scale) e = launch_fill(scale, 0.0, n, c->stream);
@@ -476,6 +479,7 @@ qgbe_status qgbe_step(qgbe_ctx* c, double dt_fm, int32_t n_samples, int32_t samp
   for (int k = 0; k < n_steps; ++k) {
     HIP_TRY(hipEventRecord(c->ev[2], c->stream), "event");
     qgbe_status s = compute_masses(c);
+    if (!s && sampler == QGBE_SAMPLER_LEARNED && c->table_net) s = refresh_proposal_table(c);
     if (s) return s;
     HIP_TRY(launch_fill(c->d_A, 0.0, n, c->stream), "zero A");
     HIP_TRY(hipEventRecord(c->ev[0], c->stream), "event");

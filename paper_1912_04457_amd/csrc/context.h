@@ -77,6 +77,10 @@ struct qgbe_ctx {
   uint32_t* d_thr = nullptr;
   float* d_mu = nullptr;
   float* d_sigma = nullptr;
+  float* d_feat = nullptr;         // [nch * nodes][8] conditioning features
+  double* d_mass7 = nullptr;       // cell-averaged masses behind d_feat
+  bool table_net = false;          // table comes from the network: rebuilt whenever the masses change
+  float table_alpha = 0.0f;        // defensive weight of that table
   qgbe::MlpState mlp;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   size_t ws = 0;
@@ -88,6 +92,9 @@ namespace qgbe {
 size_t field_len(const qgbe_ctx* c);
 qgbe_status compute_masses(qgbe_ctx* c);
 CollideArgs base_args(qgbe_ctx* c, int n_samples, double* A, double* scale, double* items);
+// Enqueue features, network forward and table construction for the current
+// masses (no allocation, no synchronisation).
+qgbe_status refresh_proposal_table(qgbe_ctx* c);
 
 template <typename T>
 qgbe_status dev_alloc(qgbe_ctx* c, T** p, size_t n, const char* what) {

@@ -208,9 +208,26 @@ __global__ void table_kernel(const float* __restrict__ Y, int rows, float alpha,
   }
 }
 
-// Conditioning inputs of every (channel, node) row at cell `cell`.
-__global__ void features_kernel(Grid G, const Channel* __restrict__ chans, int nch, const double* __restrict__ mass2,
-                                int cell, float* __restrict__ X) {
+// Per-species thermal mass squared averaged over the cells (one workgroup per
+// species, fixed summation order).
+__global__ void mass_mean_kernel(Grid G, const double* __restrict__ mass2, double* __restrict__ mean) {
+  __shared__ double part[256];
+  const int sp = blockIdx.x;
+  double s = 0.0;
+  for (int x = threadIdx.x; x < G.cells; x += blockDim.x) s += mass2[sp * G.cells + x];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) mean[sp] = part[0] / G.cells;
+}
+
+// Conditioning inputs of every (channel, node) row; the masses are the
+// per-species values in mass7 (cell averages), so one table serves all cells.
+__global__ void features_kernel(Grid G, const Channel* __restrict__ chans, int nch, const double* __restrict__ mass7,
+                                float* __restrict__ X) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= nch * G.nodes) return;
   const int ci = r / G.nodes, node = r % G.nodes;
@@ -220,14 +237,14 @@ __global__ void features_kernel(Grid G, const Channel* __restrict__ chans, int n
   const double pn = sqrt(G.ph[0] * G.ph[0] + G.ph[1] * G.ph[1] + G.ph[2] * G.ph[2]);
   const int sp = chans[ci].sp[0];
   const double a = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
-  const double E1 = sqrt(a * a + mass2[sp * G.cells + cell]);
+  const double E1 = sqrt(a * a + mass7[sp]);
   float* x = X + (size_t)r * kMlpIn;
   x[0] = (float)(p[0] / G.ph[0]);
   x[1] = (float)(p[1] / G.ph[1]);
   x[2] = (float)(p[2] / G.ph[2]);
   x[3] = (float)(a / pn);
   x[4] = (float)(E1 / pn);
-  x[5] = (float)(mass2[kGluon * G.cells + cell] / (pn * pn));
+  x[5] = (float)(mass7[kGluon] / (pn * pn));
   x[6] = (float)(sp / 3.0 - 1.0);
   x[7] = nch > 1 ? (float)(2.0 * ci / (nch - 1) - 1.0) : 0.0f;
 }
@@ -300,10 +317,12 @@ hipError_t launch_table(const float* Y, int rows, float alpha, uint32_t* thr, fl
   return hipGetLastError();
 }
 
-hipError_t launch_features(const Grid& G, const Channel* chans, int nch, const double* mass2, int cell, float* X,
+hipError_t launch_features(const Grid& G, const Channel* chans, int nch, const double* mass2, double* mass7, float* X,
                            hipStream_t st) {
+  hipLaunchKernelGGL(mass_mean_kernel, dim3(kSpecies), dim3(256), 0, st, G, mass2, mass7);
   const int rows = nch * G.nodes;
-  hipLaunchKernelGGL(features_kernel, dim3((rows + 127) / 128), dim3(128), 0, st, G, chans, nch, mass2, cell, X);
+  if (rows > 0)
+    hipLaunchKernelGGL(features_kernel, dim3((rows + 127) / 128), dim3(128), 0, st, G, chans, nch, mass7, X);
   return hipGetLastError();
 }
 

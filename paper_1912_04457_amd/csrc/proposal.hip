@@ -132,12 +132,37 @@ qgbe_status install_table_buffers(qgbe_ctx* c, int K) {
   return QGBE_OK;
 }
 
+qgbe_status ensure_feature_buffers(qgbe_ctx* c) {
+  qgbe_status s = QGBE_OK;
+  if (!c->d_feat) s = dev_alloc(c, &c->d_feat, std::max<size_t>(1, (size_t)c->nch * c->G.nodes) * kMlpIn, "features");
+  if (!s && !c->d_mass7) s = dev_alloc(c, &c->d_mass7, kSpecies, "mean masses");
+  return s;
+}
+
 qgbe_status ensure_masses(qgbe_ctx* c) {
   if (c->masses_valid) return QGBE_OK;
   return compute_masses(c);
 }
 
 }  // namespace
+
+// Features of the current (cell-averaged) masses -> network -> table, on the
+// context's stream.  Needs the weights, the table buffers (K = kMixK) and the
+// feature buffers in place.
+qgbe_status qgbe::refresh_proposal_table(qgbe_ctx* c) {
+  MlpState& m = c->mlp;
+  const int rows = c->nch * c->G.nodes;
+  HIP_TRY(launch_features(c->G, c->d_chans, c->nch, c->d_mass2, c->d_mass7, c->d_feat, c->stream), "features");
+  for (int r0 = 0; r0 < rows; r0 += kBatch) {
+    const int nr = std::min(kBatch, rows - r0);
+    HIP_TRY(launch_f32_to_bf16(c->d_feat + (size_t)r0 * kMlpIn, m.Xb, (size_t)nr * kMlpIn, c->stream), "features to bf16");
+    qgbe_status s = forward_staged(c, nr);
+    if (s) return s;
+    HIP_TRY(launch_table(m.Y, nr, c->table_alpha, c->d_thr + (size_t)r0 * kMixK, c->d_mu + (size_t)r0 * kMixK * 5,
+                         c->d_sigma + (size_t)r0 * kMixK * 5, c->stream), "proposal table");
+  }
+  return QGBE_OK;
+}
 
 extern "C" {
 
@@ -148,6 +173,7 @@ qgbe_status qgbe_set_proposal_table(qgbe_ctx* c, int32_t K, const uint32_t* thr,
   HIP_TRY(hipSetDevice(c->d.device), "hipSetDevice");
   qgbe_status s = install_table_buffers(c, K);
   if (s) return s;
+  c->table_net = false;
   const size_t rows = (size_t)c->nch * c->G.nodes;
   const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   HIP_TRY(hipMemcpyAsync(c->d_thr, thr, rows * K * sizeof(uint32_t), kind, c->stream), "copy thresholds");
@@ -246,16 +272,13 @@ qgbe_status qgbe_proposal_features(qgbe_ctx* c, float* X, int32_t on_device) {
   if (!c || !X) return fail(QGBE_EINVAL, "NULL argument");
   HIP_TRY(hipSetDevice(c->d.device), "hipSetDevice");
   qgbe_status s = ensure_masses(c);
+  if (!s) s = ensure_feature_buffers(c);
   if (s) return s;
   const size_t rows = (size_t)c->nch * c->G.nodes;
-  float* dst = X;
-  if (!on_device) HIP_TRY(hipMalloc(&dst, std::max<size_t>(1, rows) * kMlpIn * sizeof(float)), "features scratch");
-  hipError_t e = launch_features(c->G, c->d_chans, c->nch, c->d_mass2, 0, dst, c->stream);
-  if (e == hipSuccess && !on_device)
-    e = hipMemcpyAsync(X, dst, rows * kMlpIn * sizeof(float), hipMemcpyDeviceToHost, c->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  if (!on_device) (void)hipFree(dst);
-  if (e != hipSuccess) return hip_fail(e, "features");
+  HIP_TRY(launch_features(c->G, c->d_chans, c->nch, c->d_mass2, c->d_mass7, c->d_feat, c->stream), "features");
+  HIP_TRY(hipMemcpyAsync(X, c->d_feat, rows * kMlpIn * sizeof(float),
+                         on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream), "copy features");
+  HIP_TRY(hipStreamSynchronize(c->stream), "synchronise");
   return QGBE_OK;
 }
 
@@ -291,26 +314,17 @@ qgbe_status qgbe_proposal_build_table(qgbe_ctx* c, float alpha) {
   if (s) return s;
   HIP_TRY(hipSetDevice(c->d.device), "hipSetDevice");
   s = ensure_masses(c);
+  if (!s) s = install_table_buffers(c, kMixK);
+  if (!s) s = ensure_feature_buffers(c);
   if (s) return s;
-  s = install_table_buffers(c, kMixK);
-  if (s) return s;
-  MlpState& m = c->mlp;
-  const int rows = c->nch * c->G.nodes;
-  float* X = nullptr;
-  HIP_TRY(hipMalloc(&X, std::max(1, rows) * kMlpIn * sizeof(float)), "features scratch");
-  hipError_t e = launch_features(c->G, c->d_chans, c->nch, c->d_mass2, 0, X, c->stream);
-  for (int r0 = 0; r0 < rows && e == hipSuccess; r0 += kBatch) {
-    const int nr = std::min(kBatch, rows - r0);
-    e = launch_f32_to_bf16(X + (size_t)r0 * kMlpIn, m.Xb, (size_t)nr * kMlpIn, c->stream);
-    if (e != hipSuccess) break;
-    s = forward_staged(c, nr);
-    if (s) { (void)hipFree(X); return s; }
-    e = launch_table(m.Y, nr, alpha, c->d_thr + (size_t)r0 * kMixK, c->d_mu + (size_t)r0 * kMixK * 5,
-                     c->d_sigma + (size_t)r0 * kMixK * 5, c->stream);
+  c->table_alpha = alpha;
+  c->table_net = true;
+  s = refresh_proposal_table(c);
+  if (s) {
+    c->table_net = false;
+    return s;
   }
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  (void)hipFree(X);
-  if (e != hipSuccess) return hip_fail(e, "build proposal table");
+  HIP_TRY(hipStreamSynchronize(c->stream), "build proposal table");
   return QGBE_OK;
 }
 

@@ -85,34 +85,51 @@ def test_features_match_oracle(O):
         s.set_f(f)
         X = np.zeros((len(chans) * wl.nodes, 8), dtype=np.float32)
         qgbe.qgbe_proposal_features(s.ctx, X)
-    m = O.masses(g, f)
+    m = O.masses(g, f).mean(axis=1)     # one table serves all cells: cell-averaged masses
     P = g.momenta()
-    ref = np.concatenate([M.features(P, m[c["sp"][0], 0], m[6, 0], c["sp"][0], i, len(chans), wl.p_half)
+    ref = np.concatenate([M.features(P, m[c["sp"][0]], m[6], c["sp"][0], i, len(chans), wl.p_half)
                           for i, c in enumerate(chans)])
     assert np.allclose(X, ref, rtol=1e-6, atol=1e-7)
 
 
+def _table_ref(O, g, f, w, alpha):
+    chans = O.channels(g)
+    m = O.masses(g, f).mean(axis=1)
+    X = np.concatenate([M.features(g.momenta(), m[c["sp"][0]], m[6], c["sp"][0], i, len(chans), g.p_half)
+                        for i, c in enumerate(chans)])
+    Y, _ = M.forward(M.unflatten(w.astype(np.float64)), X, quantize=M.bf16)
+    return M.table_from_head(Y, float(np.float32(alpha)))   # the ABI takes alpha as FP32
+
+
+def _check_table(tab, ref):
+    thr, mu, sg = tab
+    t_ref, mu_ref, sg_ref = ref
+    assert np.all(thr[:, 0] == t_ref[:, 0])
+    assert np.abs(thr.astype(np.float64) - t_ref).max() <= 2**32 * 2e-2
+    assert _rel(mu, mu_ref) <= 1e-2 and _rel(sg, sg_ref) <= 1e-2
+
+
 def test_table_from_network(O):
+    """The table built from the network, and its re-evaluation by a learned
+    collision term after f (hence the masses) changed."""
     _case("table build")
     wl = SMALL_7
     f = W.random_f(32, wl.cells, wl.nodes)
+    f2 = W.random_f(35, wl.cells, wl.nodes) * 0.5
     w = W.random_mlp_params(7, head_scale=1.0)
     g = O.Grid(n_x=wl.n_x, n_p=wl.n_p, x_half=wl.x_half, p_half=wl.p_half, species_mask=wl.species_mask)
-    chans = O.channels(g)
-    rows = len(chans) * wl.nodes
+    rows = len(O.channels(g)) * wl.nodes
     with qgbe.Solver(**_kw(wl)) as s:
         s.set_f(f)
         qgbe.qgbe_proposal_set_weights(s.ctx, w)
         qgbe.qgbe_proposal_build_table(s.ctx, 0.1)
-        thr, mu, sg = qgbe.qgbe_get_proposal_table(s.ctx, rows)
-    m = O.masses(g, f)
-    X = np.concatenate([M.features(g.momenta(), m[c["sp"][0], 0], m[6, 0], c["sp"][0], i, len(chans), wl.p_half)
-                        for i, c in enumerate(chans)])
-    Y, _ = M.forward(M.unflatten(w.astype(np.float64)), X, quantize=M.bf16)
-    t_ref, mu_ref, sg_ref = M.table_from_head(Y, float(np.float32(0.1)))   # the ABI takes alpha as FP32
-    assert np.all(thr[:, 0] == t_ref[:, 0])
-    assert np.abs(thr.astype(np.float64) - t_ref).max() <= 2**32 * 2e-2
-    assert _rel(mu, mu_ref) <= 1e-2 and _rel(sg, sg_ref) <= 1e-2
+        tab1 = qgbe.qgbe_get_proposal_table(s.ctx, rows)
+        s.set_f(f2)
+        s.collision(8, sampler=qgbe.SAMPLER_LEARNED)
+        tab2 = qgbe.qgbe_get_proposal_table(s.ctx, rows)
+    _check_table(tab1, _table_ref(O, g, f, w, 0.1))
+    _check_table(tab2, _table_ref(O, g, f2, w, 0.1))
+    assert not np.array_equal(tab1[1], tab2[1])
 
 
 @pytest.mark.parametrize("precision,tol", [(qgbe.FP64, 1e-10), (qgbe.FP32, 1e-4)])

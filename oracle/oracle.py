@@ -91,7 +91,7 @@ def lib():
         _lib.ref_collision.restype = i32
         _lib.ref_collision.argtypes = [p, p, p, u64, u32, i32, i32, i32, i32, p, p, p, p, i32]
         _lib.ref_collision_learned.restype = i32
-        _lib.ref_collision_learned.argtypes = [p, p, p, u64, u32, i32, i32, p, p, p, i32,
+        _lib.ref_collision_learned.argtypes = [p, p, p, u64, u32, i32, i32, p, p, p, i32, p,
                                                p, p, p, i32]
         _lib.ref_item_sums.restype = i32
         _lib.ref_item_sums.argtypes = [p, p, p, u64, u32, i32, i32, C.c_int64, p, p, i32]
@@ -250,9 +250,11 @@ def collision(grid: Grid, f, mass2, seed: int, step: int, n_samples: int, *, est
 
 
 def collision_learned(grid: Grid, f, mass2, seed: int, step: int, n_samples: int, thr, mu, sigma, *,
-                      table_per_cell: bool = False, want_scale: bool = True,
+                      table_per_cell: bool = False, chan_learned=None, want_scale: bool = True,
                       want_items: bool = False, threads: int = 0):
-    """Collision term with the mixture proposal given as a table (see header)."""
+    """Collision term with the mixture proposal given as a table (see header).
+    chan_learned: per-channel 0/1 (0 = that channel falls back to the uniform
+    sampler), None = every channel uses the mixture."""
     f = _field(grid, f)
     mass2 = _mass(grid, mass2)
     thr = np.ascontiguousarray(thr, dtype=np.uint32)
@@ -263,13 +265,17 @@ def collision_learned(grid: Grid, f, mass2, seed: int, step: int, n_samples: int
     rows = (grid.cells if table_per_cell else 1) * nch * grid.nodes
     if thr.size != rows * K or mu.size != rows * K * 5 or sigma.size != rows * K * 5:
         raise ValueError("table shape does not match the grid")
+    if chan_learned is not None:
+        chan_learned = np.ascontiguousarray(chan_learned, dtype=np.uint8)
+        if chan_learned.size != nch:
+            raise ValueError("chan_learned needs one entry per channel")
     A = np.zeros_like(f)
     S = np.zeros_like(f) if want_scale else None
     items = np.zeros((grid.cells, nch, grid.nodes)) if want_items else None
     g = grid.c()
     r = lib().ref_collision_learned(C.byref(g), _ptr(f), _ptr(mass2), seed, step, n_samples, K,
                                     _ptr(thr), _ptr(mu), _ptr(sigma), int(table_per_cell),
-                                    _ptr(A), _ptr(S), _ptr(items), threads)
+                                    _ptr(chan_learned), _ptr(A), _ptr(S), _ptr(items), threads)
     if r < 0:
         raise ValueError("oracle rejected the arguments")
     return A, S, items

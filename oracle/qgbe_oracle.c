@@ -650,6 +650,7 @@ typedef struct {
   const ref_grid* g; const double* f; const double* mass2; uint64_t seed; uint32_t step;
   int32_t N; int estimator, symmetric, flags; const ref_equilibrium* eq;
   int K; const uint32_t* thr; const float* mu; const float* sg; int table_per_cell;
+  const uint8_t* chan_learned;
 } run_args;
 
 static int32_t run_all(const run_args* ra, item_kind kind, double* A_out, double* S_out,
@@ -691,7 +692,7 @@ static int32_t run_all(const run_args* ra, item_kind kind, double* A_out, double
     const int64_t p1 = rem % nn;
     accum acc = {bufA[tid], bufS[tid]};
     double* item = item_sum ? &item_sum[(cell * nch + ci) * nn + p1] : NULL;
-    if (kind == ITEM_UNIFORM) {
+    if (kind == ITEM_UNIFORM || (ra->chan_learned && !ra->chan_learned[ci])) {
       run_item_uniform(g, &chans[ci], ra->f, ra->mass2, ra->seed, ra->step, ra->N, ra->estimator,
                        ra->symmetric, ra->flags, ra->eq, cell, p1, &acc, item);
     } else {
@@ -750,7 +751,7 @@ int32_t ref_collision(const ref_grid* g, const double* f, const double* mass2,
                       double* item_sum, int32_t n_threads) {
   if ((flags & REF_ANALYTIC_F) && !eq) return -1;
   run_args ra = {g, f, mass2, seed, step, n_samples, estimator, symmetric, flags, eq,
-                 0, NULL, NULL, NULL, 0};
+                 0, NULL, NULL, NULL, 0, NULL};
   return run_all(&ra, ITEM_UNIFORM, A_out, S_out, item_sum, n_threads);
 }
 
@@ -758,11 +759,12 @@ int32_t ref_collision_learned(const ref_grid* g, const double* f, const double* 
                               uint64_t seed, uint32_t step, int32_t n_samples,
                               int32_t K, const uint32_t* thr, const float* mu,
                               const float* sigma, int32_t table_per_cell,
+                              const uint8_t* chan_learned,
                               double* A_out, double* S_out, double* item_sum,
                               int32_t n_threads) {
   if (K < 1 || K > 64) return -1;
   run_args ra = {g, f, mass2, seed, step, n_samples, REF_EST_CM, 1, 0, NULL,
-                 K, thr, mu, sigma, table_per_cell};
+                 K, thr, mu, sigma, table_per_cell, chan_learned};
   return run_all(&ra, ITEM_LEARNED, A_out, S_out, item_sum, n_threads);
 }
 

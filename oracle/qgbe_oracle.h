@@ -122,11 +122,15 @@ int32_t ref_item_sums(const ref_grid* g, const double* f, const double* mass2, u
  *              component k drawn when thr[k] <= x < thr[k+1] (thr[K] = 2^32)
  *   mu, sigma  [rows][K][5] location and scale in logit space
  *   rows       = table_cells * channels * nodes (table_cells is 1 or cells)
+ *   chan_learned [channels] 1: the channel samples from the mixture, 0: it
+ *              falls back to the uniform sampler (its draws and weight 1);
+ *              NULL: every channel uses the mixture
  */
 int32_t ref_collision_learned(const ref_grid* g, const double* f, const double* mass2,
                               uint64_t seed, uint32_t step, int32_t n_samples,
                               int32_t K, const uint32_t* thr, const float* mu,
                               const float* sigma, int32_t table_per_cell,
+                              const uint8_t* chan_learned,
                               double* A_out, double* S_out, double* item_sum,
                               int32_t n_threads);
 

@@ -196,3 +196,26 @@ def test_mixture_proposal_unbiased(O):
     # conservation is unchanged by the proposal
     A, S, _ = O.collision_learned(g, f, m, 5, 0, 100, thr, mu, sg)
     assert abs(A.sum()) <= 1e-13 * S.sum()
+
+
+def test_channel_fallback_routes_to_the_uniform_sampler(O):
+    """Channels flagged 0 take the uniform sampler's draws and weight exactly;
+    channels flagged 1 are unchanged (item sums compared channel by channel)."""
+    g = O.Grid(n_p=(4, 4, 4), p_half=(2.0, 2.0, 2.0), species_mask=(1 << 0) | (1 << 3) | (1 << G))
+    f = W.smooth_f(1, g.n_p, g.p_half, species_mask=g.species_mask)
+    m = O.masses(g, f)
+    nch = len(O.channels(g))
+    thr, mu, sg = W.random_mog_table(10, nch * g.nodes, K=4, alpha=0.25, mu_scale=0.8,
+                                     log_sigma=(-0.3, 0.5))
+    A_u, _, it_u = O.collision(g, f, m, SEED, 7, 50, want_items=True, threads=1)
+    A_f, _, it_f = O.collision_learned(g, f, m, SEED, 7, 50, thr, mu, sg, chan_learned=np.zeros(nch),
+                                       want_items=True, threads=1)
+    assert np.array_equal(A_u, A_f) and np.array_equal(it_u, it_f)
+    flags = np.arange(nch) % 2
+    _, _, it_l = O.collision_learned(g, f, m, SEED, 7, 50, thr, mu, sg, want_items=True, threads=1)
+    _, _, it_m = O.collision_learned(g, f, m, SEED, 7, 50, thr, mu, sg, chan_learned=flags,
+                                     want_items=True, threads=1)
+    for ci in range(nch):
+        ref = it_l if flags[ci] else it_u
+        assert np.array_equal(it_m[:, ci], ref[:, ci]), ci
+    assert not np.array_equal(it_l, it_u)

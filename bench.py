@@ -124,6 +124,12 @@ def fixed_error(R):
         out.update(train_rows=n_rows, train_epochs=epochs, train_s=time.perf_counter() - t0,
                    train_loss_first=float(losses[0]), train_loss_last=float(losses[-1]))
         del rows
+        # fallback judge: channels whose pilot variance x time is not lower
+        # with the learned sampler go back to the uniform one
+        t0 = time.perf_counter()
+        flags, _ = qgbe.qgbe_proposal_judge(solver.ctx, 256, 4, solver.n_channels)
+        out.update(judge_s=time.perf_counter() - t0, learned_channels=int(flags.sum()),
+                   channels=solver.n_channels)
 
         cache = {}
 

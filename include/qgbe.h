@@ -151,6 +151,22 @@ qgbe_status qgbe_get_masses(qgbe_ctx* ctx, double* mass2);
 qgbe_status qgbe_set_step_index(qgbe_ctx* ctx, uint32_t step);
 qgbe_status qgbe_get_step_index(const qgbe_ctx* ctx, uint32_t* step);
 
+/* Serialise the evolving state into a host buffer: f, the step index, the
+ * lagged masses the next mass evaluation will use, and the learned proposal
+ * (network weights with their Adam moments, proposal table).  buf = NULL:
+ * *bytes receives the size needed.  Otherwise *bytes is the buffer size on
+ * entry (QGBE_EINVAL, with the size needed in *bytes, if too small) and the
+ * size written on return.  The caller owns buf.  Synchronises the stream. */
+qgbe_status qgbe_checkpoint(qgbe_ctx* ctx, void* buf, size_t* bytes);
+
+/* Load a buffer written by qgbe_checkpoint into a context created with the
+ * same descriptor (grid, species and rows, alpha_s, precision, symmetric,
+ * drift, mass mode and seed; device and stream may differ).  QGBE_EINVAL for
+ * a foreign, truncated or mismatching buffer, before any device work.  A run
+ * continued from the restored state draws the same samples as the original
+ * run would have. */
+qgbe_status qgbe_restore(qgbe_ctx* ctx, const void* buf, size_t bytes);
+
 /* ---- the hot path ------------------------------------------------------- */
 
 /* The Monte Carlo collision term A = N_Y C_Y for every cell, species and node
@@ -197,6 +213,26 @@ qgbe_status qgbe_observables(qgbe_ctx* ctx, qgbe_stats* st);
  * rows = channels * nodes.  K in 1..16.  Copied into the workspace. */
 qgbe_status qgbe_set_proposal_table(qgbe_ctx* ctx, int32_t K, const uint32_t* thr,
                                     const float* mu, const float* sigma, int32_t on_device);
+
+/* Per-channel sampler choice of the learned mode: use_learned[channels], 1 =
+ * the channel draws from the proposal table, 0 = it falls back to the uniform
+ * sampler (the same draws and weights as QGBE_SAMPLER_UNIFORM).  Installing a
+ * table (qgbe_set_proposal_table, qgbe_proposal_build_table, training) sets
+ * every channel to 1.  QGBE_ESTATE without a table. */
+qgbe_status qgbe_set_channel_samplers(qgbe_ctx* ctx, const uint8_t* use_learned);
+qgbe_status qgbe_get_channel_samplers(qgbe_ctx* ctx, uint8_t* use_learned);
+
+/* The fallback judge of the learned proposal: n_reps pilot collision terms of
+ * n_pilot samples per point with each sampler (on a key range of their own),
+ * then per channel the summed variance of the per-(cell, node) estimates
+ * times the sampler's pilot time; a channel keeps the learned sampler only if
+ * that product is smaller than the uniform one.  Installs the decision and
+ * returns it in use_learned[channels] (may be NULL); ratio[channels] (may be
+ * NULL) receives learned / uniform variance x time.  The step index and f are
+ * left as they were.  Allocates a pilot buffer of cells*channels*nodes
+ * doubles for the call. */
+qgbe_status qgbe_proposal_judge(qgbe_ctx* ctx, int32_t n_pilot, int32_t n_reps, uint8_t* use_learned,
+                                double* ratio);
 
 /* ---- the learned proposal (a network that writes the proposal table) ---- */
 /*

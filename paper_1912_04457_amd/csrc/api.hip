@@ -65,6 +65,7 @@ CollideArgs base_args(qgbe_ctx* c, int n_samples, double* A, double* scale, doub
   a.mix_thr = c->d_thr;
   a.mix_mu = c->d_mu;
   a.mix_sigma = c->d_sigma;
+  a.mix_on = c->d_mix_on;
   return a;
 }
 
@@ -121,22 +122,28 @@ void make_grid(const qgbe_grid_desc* d, Grid& G) {
   G.species_mask = d->species_mask;
 }
 
-// LDS plan: FP64 accumulators first (they replace global atomics), then FP32
-// f tiles in what is left; slots that do not fit use global memory.
+// LDS plan per sampler: FP64 accumulators first (they replace global
+// atomics), then FP32 f tiles in what is left; slots that do not fit use
+// global memory.
 void plan_groups(qgbe_ctx* c) {
-  const size_t budget = c->lds_bytes;
   const size_t acc_b = (size_t)c->G.nodes * sizeof(double);
   const size_t tile_b = (size_t)c->G.nodes * sizeof(float);
   c->group_index.clear();
   c->groups.clear();
   for (int nslot = 1; nslot <= 3; ++nslot) {
-    Group g{(int)c->group_index.size(), 0, nslot, 0, 0};
-    g.lds_acc = c->d.symmetric ? (int)std::min<size_t>(nslot, budget / acc_b) : 0;
-    g.lds_tiles = (int)std::min<size_t>(nslot, (budget - g.lds_acc * acc_b) / tile_b);
+    Group g{(int)c->group_index.size(), 0, nslot, {0, 0}, {0, 0}};
+    for (int l = 0; l < 2; ++l) {
+      const size_t budget = c->lds_budget[l];
+      g.lds_acc[l] = c->d.symmetric ? (int)std::min<size_t>(nslot, budget / acc_b) : 0;
+      g.lds_tiles[l] = (int)std::min<size_t>(nslot, (budget - g.lds_acc[l] * acc_b) / tile_b);
+    }
     for (int i = 0; i < c->nch; ++i)
       if (c->chans[i].nslot == nslot) c->group_index.push_back(i);
     g.count = (int)c->group_index.size() - g.start;
-    if (g.count) c->groups.push_back(g);
+    if (g.count) {
+      c->groups.push_back(g);
+      for (int l = 0; l < 2; ++l) c->need_quads[l] = c->need_quads[l] || g.lds_tiles[l] < nslot;
+    }
   }
 }
 
@@ -146,6 +153,9 @@ qgbe_status run_collide(qgbe_ctx* c, int n_samples, bool learned, double* A, dou
   if (c->nch == 0) return QGBE_OK;
   CollideArgs a = base_args(c, n_samples, A, scale, items);
   a.learned = learned ? 1 : 0;
+  a.slot_lo = 0;
+  a.slot_hi = 3;
+  a.direct = 1;
   const bool f64_path = c->d.precision == QGBE_FP64;
   if (f64_path) {
     a.group = c->d_all;
@@ -153,7 +163,10 @@ qgbe_status run_collide(qgbe_ctx* c, int n_samples, bool learned, double* A, dou
     HIP_TRY(launch_collide_f64(a, c->stream), "collide (fp64)");
     return QGBE_OK;
   }
-  const int waves = 8;
+  const int waves = collide_f32_waves(learned);
+  const int l = learned ? 1 : 0;
+  if (c->need_quads[l]) HIP_TRY(launch_f32_quads(c->G, c->d_f32, c->d_f32q, c->stream), "f32 quads");
+  a.f32q = c->d_f32q;
   for (const Group& g : c->groups) {
     a.group = c->d_groups + g.start;
     a.n_group = g.count;
@@ -164,9 +177,26 @@ qgbe_status run_collide(qgbe_ctx* c, int n_samples, bool learned, double* A, dou
     chunk = std::min<long long>(chunk, (c->G.nodes + waves - 1) / waves * waves);
     a.chunk_items = (int)chunk;
     a.n_chunks = (int)((c->G.nodes + chunk - 1) / chunk);
-    a.lds_tiles = g.lds_tiles;
-    a.lds_acc = g.lds_acc;
-    HIP_TRY(launch_collide_f32(a, g.nslot, c->stream), "collide (fp32)");
+    // Deposit slots whose FP64 accumulators do not all fit in LDS are split
+    // over launches that each keep their slots' accumulators in LDS: the
+    // samples are recomputed (same draws), which costs far less than global
+    // FP64 atomics on every deposit.  The first launch also writes the direct
+    // sums.  Without room for even one accumulator, global atomics remain.
+    const int per = g.lds_acc[l];
+    const int n_pass = (c->d.symmetric && per >= 1 && per < g.nslot) ? (g.nslot + per - 1) / per : 1;
+    const size_t acc_b = (size_t)c->G.nodes * sizeof(double), tile_b = (size_t)c->G.nodes * sizeof(float);
+    for (int pass = 0; pass < n_pass; ++pass) {
+      a.slot_lo = n_pass > 1 ? pass * per : 0;
+      a.slot_hi = n_pass > 1 ? std::min(g.nslot, a.slot_lo + per) : g.nslot;
+      a.direct = pass == 0 ? 1 : 0;
+      a.lds_acc = g.lds_acc[l];
+      a.lds_tiles = g.lds_tiles[l];
+      if (n_pass > 1) {
+        const size_t used = (size_t)(a.slot_hi - a.slot_lo) * acc_b;
+        a.lds_tiles = (int)std::min<size_t>(g.nslot, (c->lds_budget[l] - used) / tile_b);
+      }
+      HIP_TRY(launch_collide_f32(a, g.nslot, c->stream), "collide (fp32)");
+    }
   }
   return QGBE_OK;
 }
@@ -251,6 +281,12 @@ qgbe_status qgbe_init_grid(const qgbe_grid_desc* desc, qgbe_ctx** out) {
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(QGBE_EDEVICE, "no HIP device");
   if (desc->device < 0 || desc->device >= ndev) return fail(QGBE_EINVAL, "device ordinal out of range");
   HIP_TRY(hipSetDevice(desc->device), "hipSetDevice");
+  int lds_max = 0;
+  HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, desc->device),
+          "query LDS size");
+  size_t lds_budget[2] = {0, 0};
+  HIP_TRY(set_collide_lds_limit((size_t)std::max(lds_max, 0), &lds_budget[0], &lds_budget[1]),
+          "raise the dynamic LDS limit");
   qgbe_ctx* c = new qgbe_ctx();
   c->d = *desc;
   c->stream = (hipStream_t)desc->stream;
@@ -258,10 +294,8 @@ qgbe_status qgbe_init_grid(const qgbe_grid_desc* desc, qgbe_ctx** out) {
   c->chans.resize(kMaxChannels);
   c->nch = build_channels(desc->species_mask, desc->row_mask, c->chans.data(), kMaxChannels);
   c->chans.resize(c->nch);
-  int lds_max = 0;
-  HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, desc->device),
-          "query LDS size");
-  c->lds_bytes = lds_max > (int)kStaticLds ? (size_t)lds_max - kStaticLds : 0;
+  c->lds_budget[0] = lds_budget[0];
+  c->lds_budget[1] = lds_budget[1];
   plan_groups(c);
   const size_t n = field_len(c);
   std::vector<int> all(std::max(1, c->nch));
@@ -277,6 +311,7 @@ qgbe_status qgbe_init_grid(const qgbe_grid_desc* desc, qgbe_ctx** out) {
   ALLOC(c->d_f, n, "f");
   ALLOC(c->d_f_next, n, "f (next)");
   ALLOC(c->d_f32, n, "f (fp32)");
+  if (c->d.precision == QGBE_FP32 && (c->need_quads[0] || c->need_quads[1])) ALLOC(c->d_f32q, n, "f (fp32 quads)");
   ALLOC(c->d_A, n, "collision term");
   ALLOC(c->d_mass2, (size_t)kSpecies * c->G.cells, "masses");
   ALLOC(c->d_lag, (size_t)kSpecies * c->G.cells, "lagged masses");
@@ -294,10 +329,6 @@ qgbe_status qgbe_init_grid(const qgbe_grid_desc* desc, qgbe_ctx** out) {
   if (e == hipSuccess) {
     what = "copy channel list";
     e = hipMemcpy(c->d_all, all.data(), all.size() * sizeof(int), hipMemcpyHostToDevice);
-  }
-  if (e == hipSuccess) {
-    what = "raise the dynamic LDS limit";
-    e = set_collide_lds_limit(c->lds_bytes);
   }
   for (int i = 0; i < 4 && e == hipSuccess; ++i) {
     what = "create events";
@@ -332,6 +363,7 @@ void qgbe_destroy(qgbe_ctx* c) {
   (void)hipFree(c->d_f);
   (void)hipFree(c->d_f_next);
   (void)hipFree(c->d_f32);
+  (void)hipFree(c->d_f32q);
   (void)hipFree(c->d_A);
   (void)hipFree(c->d_mass2);
   (void)hipFree(c->d_lag);
@@ -342,6 +374,7 @@ void qgbe_destroy(qgbe_ctx* c) {
   (void)hipFree(c->d_mu);
   (void)hipFree(c->d_sigma);
   (void)hipFree(c->d_feat);
+  (void)hipFree(c->d_mix_on);
   (void)hipFree(c->d_mass7);
   {
     MlpState& m = c->mlp;

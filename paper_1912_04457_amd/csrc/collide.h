@@ -15,11 +15,15 @@ struct CollideArgs {
   int chunk_items;        // observed nodes per workgroup (FP32 kernel)
   int lds_tiles;          // f tiles staged in LDS (FP32 kernel)
   int lds_acc;            // FP64 deposit accumulators in LDS (FP32 kernel)
+  int slot_lo, slot_hi;   // deposit slots [lo, hi) written by this launch (FP32 kernel); the
+                          // first lds_acc of them accumulate in LDS, the rest in global memory
+  int direct;             // this launch also writes the direct sums, items, scale and counts
   int n_samples;
   int symmetric;
   uint32_t key0, key1;    // Philox key
   const double* f64;      // [7][cells][nodes]
   const float* f32;       // FP32 shadow of f64
+  const float4* f32q;     // node quads of f32 (global-memory tiles), see launch_f32_quads
   const double* mass2;    // [7][cells]
   double* A;              // [7][cells][nodes], accumulated into
   double* scale;          // optional, same shape
@@ -30,11 +34,17 @@ struct CollideArgs {
   const uint32_t* mix_thr;   // [channels*nodes][K]
   const float* mix_mu;       // [channels*nodes][K][5]
   const float* mix_sigma;    // [channels*nodes][K][5]
+  const uint8_t* mix_on;     // [channels] 0: the channel falls back to the uniform sampler; NULL: all 1
 };
 
 hipError_t launch_collide_f64(const CollideArgs& a, hipStream_t stream);
 hipError_t launch_collide_f32(const CollideArgs& a, int nslot, hipStream_t stream);
-hipError_t set_collide_lds_limit(size_t bytes);
+// Raise the FP32 kernels' dynamic LDS limit to what their static LDS leaves
+// of lds_max; returns the dynamic budget of the uniform-sampler and of the
+// learned-sampler variants.
+hipError_t set_collide_lds_limit(size_t lds_max, size_t* budget_plain, size_t* budget_learned);
+// Waves per workgroup of the FP32 kernel (chunks are multiples of it).
+int collide_f32_waves(bool learned);
 hipError_t launch_record(const CollideArgs& a, int n_per_item, long long item_stride, long long n_sel, float* rows,
                          hipStream_t stream);
 

@@ -55,6 +55,41 @@ __device__ __forceinline__ double rsqrt64(double x) {
 }
 
 // sqrt for x >= 0 (0 maps to 0)
+// sin and cos of 2 pi u for u in [0, 1).  With x = 2u = q/2 + r, q the
+// nearest multiple of 1/2 (exact: u has at most 24 significant bits) and
+// |r| <= 1/4, the Taylor series of sin(pi r) to r^15 and of cos(pi r) to
+// r^16 are accurate to 3e-17 and 2e-18, and the quadrant q mod 4 permutes
+// and negates them.
+__device__ __forceinline__ void sincos_2pi(double u, double& sn, double& cs) {
+  const double x = 2.0 * u;
+  const double q = rint(2.0 * x);
+  const double r = fma(-0.5, q, x);
+  const double r2 = r * r;
+  double ps = -2.1915353447830217e-05;
+  ps = fma(ps, r2, 0.00046630280576761255);
+  ps = fma(ps, r2, -0.0073704309457143504);
+  ps = fma(ps, r2, 0.08214588661112823);
+  ps = fma(ps, r2, -0.5992645293207921);
+  ps = fma(ps, r2, 2.5501640398773455);
+  ps = fma(ps, r2, -5.16771278004997);
+  ps = fma(ps, r2, 3.141592653589793);
+  ps *= r;
+  double pc = 4.303069587032947e-06;
+  pc = fma(pc, r2, -0.0001046381049248457);
+  pc = fma(pc, r2, 0.0019295743094039231);
+  pc = fma(pc, r2, -0.02580689139001406);
+  pc = fma(pc, r2, 0.2353306303588932);
+  pc = fma(pc, r2, -1.3352627688545895);
+  pc = fma(pc, r2, 4.0587121264167685);
+  pc = fma(pc, r2, -4.934802200544679);
+  pc = fma(pc, r2, 1.0);
+  const int k = (int)q;
+  const double a = (k & 1) ? pc : ps;   // sin before the sign
+  const double b = (k & 1) ? ps : pc;   // cos before the sign
+  sn = (k & 2) ? -a : a;
+  cs = ((k + 1) & 2) ? -b : b;
+}
+
 __device__ __forceinline__ double sqrt64(double x) { return x > 0.0 ? x * rsqrt64(x) : 0.0; }
 
 template <typename R>
@@ -96,12 +131,8 @@ struct Stencil {
 // a relative (not an absolute 2^-24 * n) error when rounded to R.
 template <typename R>
 __device__ __forceinline__ R clamp_axis(double p, double ph, double inv_dp, int n, int& i0) {
-  double t = fma(p + ph, inv_dp, -0.5);
-  t = t < 0.0 ? 0.0 : t;
-  const double top = (double)(n - 1);
-  t = t > top ? top : t;
-  int i = (int)t;
-  i = i > n - 2 ? n - 2 : i;
+  const double t = fmin(fmax(fma(p + ph, inv_dp, -0.5), 0.0), (double)(n - 1));
+  const int i = min((int)t, n - 2);
   i0 = i;
   return (R)(t - (double)i);
 }
@@ -204,7 +235,7 @@ __device__ __forceinline__ bool geometry(const Item& it, const Grid& G, const do
   const double cth = 2.0 * u[3] - 1.0;
   const double sth = 2.0 * sqrt64(u[3] * (1.0 - u[3]));
   double sphi, cphi;
-  sincospi(2.0 * u[4], &sphi, &cphi);
+  sincos_2pi(u[4], sphi, cphi);
   const double sc = sth * cphi, ss = sth * sphi;
   double p3s[3];
   for (int k = 0; k < 3; ++k) p3s[k] = g.pstar * (sc * e1[k] + ss * e2[k] + cth * n[k]);
@@ -439,12 +470,13 @@ __global__ __launch_bounds__(256) void collide_f64_kernel(CollideArgs A) {
     double dsum = 0.0, ssum = 0.0;
     int n_ok = 0;
     const size_t mrow = (size_t)ci * G.nodes + p1_lin;
+    const bool mix = kLearned && (!A.mix_on || A.mix_on[ci]);
     for (int s = lane; s < A.n_samples; s += kWave) {
       uint32_t x0 = (uint32_t)s, x1 = (uint32_t)p1_lin, x2 = (uint32_t)cell, x3 = ((uint32_t)ch.code << 8);
       philox4x32_10(x0, x1, x2, x3, A.key0, A.key1);
       double u[5];
       double inv_q = 1.0;
-      if (kLearned) {
+      if (mix) {
         uint32_t y0 = (uint32_t)s, y1 = (uint32_t)p1_lin, y2 = (uint32_t)cell, y3 = ((uint32_t)ch.code << 8) | 1u;
         philox4x32_10(y0, y1, y2, y3, A.key0, A.key1);
         const uint32_t xw[8] = {x0, x1, x2, x3, y0, y1, y2, y3};
@@ -505,11 +537,31 @@ __global__ __launch_bounds__(256) void collide_f64_kernel(CollideArgs A) {
 // deposit with FP64 atomics into the output / read f from global memory.  The
 // accumulators are flushed into the FP64 output once per workgroup.
 // ---------------------------------------------------------------------------
+// Trilinear read from the node quads: the same corners and the same
+// arithmetic as interpolate, in two 16-byte loads.
+template <typename R>
+__device__ __forceinline__ R interpolate_quads(const float4* __restrict__ q4, const Stencil<R>& st, int ox) {
+  typedef float V4 __attribute__((ext_vector_type(4)));
+  typedef __attribute__((address_space(1))) const V4 GlobalV4;
+  const V4 lo = ((GlobalV4*)q4)[st.base];
+  const V4 hi = ((GlobalV4*)q4)[st.base + ox];
+  const R a00 = (R)lo.x + st.wz * ((R)lo.y - (R)lo.x);
+  const R a01 = (R)lo.z + st.wz * ((R)lo.w - (R)lo.z);
+  const R a10 = (R)hi.x + st.wz * ((R)hi.y - (R)hi.x);
+  const R a11 = (R)hi.z + st.wz * ((R)hi.w - (R)hi.z);
+  const R b0 = a00 + st.wy * (a01 - a00);
+  const R b1 = a10 + st.wy * (a11 - a10);
+  return b0 + st.wx * (b1 - b0);
+}
+
 template <bool kTilesLds, typename R>
-__device__ __forceinline__ R interp_slot(int k, int n_tiles, const float* tiles, const float* __restrict__ f32,
-                                         const size_t* goff, const Stencil<R>& st, int nodes, int ox, int oy) {
-  if (kTilesLds || k < n_tiles) return interpolate<R>(tiles + k * nodes, st, ox, oy);
-  return interpolate<R>(f32 + goff[k], st, ox, oy);
+__device__ __forceinline__ R interp_slot(int k, int n_tiles, const float* tiles, const float4* __restrict__ f32q,
+                                         size_t off, const Stencil<R>& st, int nodes, int ox, int oy) {
+  // an address-space-qualified view keeps the LDS reads ds_read instructions
+  // instead of generic flat loads
+  typedef __attribute__((address_space(3))) const float LdsF32;
+  if (kTilesLds || k < n_tiles) return interpolate<R>((LdsF32*)(tiles + k * nodes), st, ox, oy);
+  return interpolate_quads<R>(f32q + off, st, ox);
 }
 
 // The corner values are split in FP64 from the FP32 value and weights (both
@@ -518,17 +570,23 @@ __device__ __forceinline__ Stencil<double> widen(const Stencil<float>& st) {
   return Stencil<double>{st.base, (double)st.wx, (double)st.wy, (double)st.wz};
 }
 
-__device__ __forceinline__ void deposit_slot(int k, int n_acc, double* acc, double* __restrict__ out,
-                                             const size_t* goff, const Stencil<float>& st, float v, int nodes,
-                                             int ox, int oy) {
-  if (k < n_acc) deposit<double, double, __HIP_MEMORY_SCOPE_WORKGROUP>(acc + k * nodes, widen(st), (double)v, ox, oy);
-  else deposit<double, double>(out + goff[k], widen(st), (double)v, ox, oy);
+__device__ __forceinline__ void deposit_slot(int k, int slot_lo, int slot_hi, int n_acc, double* acc,
+                                             double* __restrict__ out, size_t off, const Stencil<float>& st,
+                                             float v, int nodes, int ox, int oy) {
+  if (k < slot_lo || k >= slot_hi) return;  // deposited by another launch
+  const int j = k - slot_lo;
+  if (j < n_acc) deposit<double, double, __HIP_MEMORY_SCOPE_WORKGROUP>(acc + j * nodes, widen(st), (double)v, ox, oy);
+  else deposit<double, double>(out + off, widen(st), (double)v, ox, oy);
 }
 
+// Workgroup size: 12 waves for the uniform sampler (3 per SIMD at the
+// kernel's register count), 8 for the learned one (more registers per lane).
+constexpr int f32_threads(bool learned) { return learned ? 512 : 768; }
+
 template <bool kSym, bool kScale, bool kTilesLds, bool kLearned>
-__global__ __launch_bounds__(512) void collide_f32_kernel(CollideArgs A) {
+__global__ __launch_bounds__(f32_threads(kLearned)) void collide_f32_kernel(CollideArgs A) {
   extern __shared__ double lds[];
-  __shared__ float mix_rows[kLearned ? 8 : 1][kLearned ? kMixRow : 1];
+  __shared__ float mix_rows[kLearned ? f32_threads(true) / kWave : 1][kLearned ? kMixRow : 1];
   const Grid& G = A.G;
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
@@ -540,9 +598,9 @@ __global__ __launch_bounds__(512) void collide_f32_kernel(CollideArgs A) {
   const Channel ch = A.chans[ci];
   const int nslot = ch.nslot;
   const int nodes = G.nodes;
-  const int n_acc = kSym ? min(nslot, A.lds_acc) : 0;
+  const int n_acc = kSym ? min(A.slot_hi - A.slot_lo, A.lds_acc) : 0;
   const int n_tiles = min(nslot, A.lds_tiles);
-  double* acc = lds;                                          // [n_acc][nodes]
+  double* acc = lds;                                          // [n_acc][nodes], slots slot_lo..
   float* tiles = reinterpret_cast<float*>(lds + (size_t)n_acc * nodes);  // [n_tiles][nodes]
   size_t goff[3];  // offsets of the slots' (species, cell) rows in f32 and A
   for (int k = 0; k < 3; ++k) {
@@ -554,6 +612,8 @@ __global__ __launch_bounds__(512) void collide_f32_kernel(CollideArgs A) {
     for (int i = threadIdx.x; i < nodes; i += blockDim.x) tiles[k * nodes + i] = A.f32[goff[k] + i];
   __syncthreads();
   const int k2 = ch.pos_slot[0], k3 = ch.pos_slot[1], k4 = ch.pos_slot[2];
+  // row offsets of positions 2, 3, 4 (scalars: no dynamically indexed array in the loop)
+  const size_t off2 = goff[k2], off3 = goff[k3], off4 = goff[k4];
   const bool g1 = is_gluon(ch.sp[0]), g2 = is_gluon(ch.sp[1]);
   const bool g3 = is_gluon(ch.sp[2]), g4 = is_gluon(ch.sp[3]);
   const int first = chunk * A.chunk_items;
@@ -562,7 +622,7 @@ __global__ __launch_bounds__(512) void collide_f32_kernel(CollideArgs A) {
     Item it;
     load_item(it, A, ch, cell, p1_lin);
     if (!(it.E1 > 0.0)) {  // massless p = 0 node: zero measure
-      if (lane == 0 && A.items) A.items[((size_t)cell * A.n_channels + ci) * nodes + p1_lin] = 0.0;
+      if (lane == 0 && A.items && A.direct) A.items[((size_t)cell * A.n_channels + ci) * nodes + p1_lin] = 0.0;
       continue;
     }
     const float f1 = (float)it.f1;
@@ -570,19 +630,52 @@ __global__ __launch_bounds__(512) void collide_f32_kernel(CollideArgs A) {
     double dsum = 0.0, ssum = 0.0;
     int n_ok = 0;
     const size_t mrow = (size_t)ci * nodes + p1_lin;
-    if (kLearned) {
+    const bool mix = kLearned && (!A.mix_on || A.mix_on[ci]);
+    if (mix) {
       mix_prepare_f32(A.mix_thr + mrow * A.mix_K, A.mix_mu + mrow * A.mix_K * 5, A.mix_sigma + mrow * A.mix_K * 5,
                       A.mix_K, mix_rows[wid], lane);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
+    // One sample from its five uniforms: FP64 geometry (the decision), FP32
+    // integrand, direct sum and deposits.
+    auto evaluate = [&](const double u[5], float inv_q) {
+      Geo g;
+      if (!geometry(it, G, u, g)) return;
+      ++n_ok;
+      const float wnb = weight_no_bracket<float>(it, g, ch.row) * inv_q;
+      const Stencil<float> s2 = make_stencil<float>(g.p2, G);
+      const Stencil<float> s3 = make_stencil<float>(g.p3, G);
+      const Stencil<float> s4 = make_stencil<float>(g.p4, G);
+      const float f2 = interp_slot<kTilesLds, float>(k2, n_tiles, tiles, A.f32q, off2, s2, nodes, G.ox, G.oy);
+      const float f3 = interp_slot<kTilesLds, float>(k3, n_tiles, tiles, A.f32q, off3, s3, nodes, G.ox, G.oy);
+      const float f4 = interp_slot<kTilesLds, float>(k4, n_tiles, tiles, A.f32q, off4, s4, nodes, G.ox, G.oy);
+      const float F2 = g2 ? 1.0f + f2 : 1.0f - f2;
+      const float F3 = g3 ? 1.0f + f3 : 1.0f - f3;
+      const float F4 = g4 ? 1.0f + f4 : 1.0f - f4;
+      const float gain = f3 * f4 * F1 * F2, loss = f1 * f2 * F3 * F4;
+      const float v = wnb * (gain - loss);
+      dsum += (double)v;
+      if (kScale) ssum += (double)(fabsf(wnb) * (gain + loss));
+      if (kSym) {
+        deposit_slot(k2, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off2, s2, v, nodes, G.ox, G.oy);
+        deposit_slot(k3, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off3, s3, -v, nodes, G.ox, G.oy);
+        deposit_slot(k4, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off4, s4, -v, nodes, G.ox, G.oy);
+        if (kScale && A.direct) {
+          const float vs = fabsf(wnb) * (gain + loss);
+          deposit<double, double>(A.scale + ((size_t)ch.sp[1] * G.cells + cell) * nodes, widen(s2), (double)vs, G.ox, G.oy);
+          deposit<double, double>(A.scale + ((size_t)ch.sp[2] * G.cells + cell) * nodes, widen(s3), (double)vs, G.ox, G.oy);
+          deposit<double, double>(A.scale + ((size_t)ch.sp[3] * G.cells + cell) * nodes, widen(s4), (double)vs, G.ox, G.oy);
+        }
+      }
+    };
     for (int s = lane; s < A.n_samples; s += kWave) {
       uint32_t x0 = (uint32_t)s, x1 = (uint32_t)p1_lin, x2 = (uint32_t)cell, x3 = ((uint32_t)ch.code << 8);
       philox4x32_10(x0, x1, x2, x3, A.key0, A.key1);
       double u[5];
       float inv_q = 1.0f;
-      if (kLearned) {
+      if (mix) {
         uint32_t y0 = (uint32_t)s, y1 = (uint32_t)p1_lin, y2 = (uint32_t)cell, y3 = ((uint32_t)ch.code << 8) | 1u;
         philox4x32_10(y0, y1, y2, y3, A.key0, A.key1);
         const uint32_t xw[8] = {x0, x1, x2, x3, y0, y1, y2, y3};
@@ -593,35 +686,9 @@ __global__ __launch_bounds__(512) void collide_f32_kernel(CollideArgs A) {
       } else {
         five_uniforms(x0, x1, x2, x3, u);
       }
-      Geo g;
-      if (!geometry(it, G, u, g)) continue;
-      ++n_ok;
-      const float wnb = weight_no_bracket<float>(it, g, ch.row) * inv_q;
-      const Stencil<float> s2 = make_stencil<float>(g.p2, G);
-      const Stencil<float> s3 = make_stencil<float>(g.p3, G);
-      const Stencil<float> s4 = make_stencil<float>(g.p4, G);
-      const float f2 = interp_slot<kTilesLds, float>(k2, n_tiles, tiles, A.f32, goff, s2, nodes, G.ox, G.oy);
-      const float f3 = interp_slot<kTilesLds, float>(k3, n_tiles, tiles, A.f32, goff, s3, nodes, G.ox, G.oy);
-      const float f4 = interp_slot<kTilesLds, float>(k4, n_tiles, tiles, A.f32, goff, s4, nodes, G.ox, G.oy);
-      const float F2 = g2 ? 1.0f + f2 : 1.0f - f2;
-      const float F3 = g3 ? 1.0f + f3 : 1.0f - f3;
-      const float F4 = g4 ? 1.0f + f4 : 1.0f - f4;
-      const float gain = f3 * f4 * F1 * F2, loss = f1 * f2 * F3 * F4;
-      const float v = wnb * (gain - loss);
-      dsum += (double)v;
-      if (kScale) ssum += (double)(fabsf(wnb) * (gain + loss));
-      if (kSym) {
-        deposit_slot(k2, n_acc, acc, A.A, goff, s2, v, nodes, G.ox, G.oy);
-        deposit_slot(k3, n_acc, acc, A.A, goff, s3, -v, nodes, G.ox, G.oy);
-        deposit_slot(k4, n_acc, acc, A.A, goff, s4, -v, nodes, G.ox, G.oy);
-        if (kScale) {
-          const float vs = fabsf(wnb) * (gain + loss);
-          deposit<double, double>(A.scale + ((size_t)ch.sp[1] * G.cells + cell) * nodes, widen(s2), (double)vs, G.ox, G.oy);
-          deposit<double, double>(A.scale + ((size_t)ch.sp[2] * G.cells + cell) * nodes, widen(s3), (double)vs, G.ox, G.oy);
-          deposit<double, double>(A.scale + ((size_t)ch.sp[3] * G.cells + cell) * nodes, widen(s4), (double)vs, G.ox, G.oy);
-        }
-      }
+      evaluate(u, inv_q);
     }
+    if (!A.direct) continue;
     dsum = wave_sum(dsum);
     if (kScale) ssum = wave_sum(ssum);
     const int ok_total = wave_count(n_ok);
@@ -637,8 +704,8 @@ __global__ __launch_bounds__(512) void collide_f32_kernel(CollideArgs A) {
     for (int i = threadIdx.x; i < n_acc * nodes; i += blockDim.x) {
       const double v = acc[i];
       if (v != 0.0) {
-        const int k = i / nodes;
-        atomicAdd(A.A + goff[k] + (i - k * nodes), v);
+        const int j = i / nodes;
+        atomicAdd(A.A + goff[A.slot_lo + j] + (i - j * nodes), v);
       }
     }
   }
@@ -743,9 +810,11 @@ void launch_f32_sampler(const CollideArgs& a, bool tiles_lds, dim3 grid, dim3 bl
   else launch_f32_variant<kSym, kScale, false>(a, tiles_lds, grid, block, lds, st);
 }
 
+int collide_f32_waves(bool learned) { return f32_threads(learned) / kWave; }
+
 hipError_t launch_collide_f32(const CollideArgs& a, int nslot, hipStream_t stream) {
-  const int threads = 512;
-  const int n_acc = a.symmetric ? std::min(nslot, a.lds_acc) : 0;
+  const int threads = f32_threads(a.learned != 0);
+  const int n_acc = a.symmetric ? std::min(a.slot_hi - a.slot_lo, a.lds_acc) : 0;
   const int n_tiles = std::min(nslot, a.lds_tiles);
   const bool tiles_lds = n_tiles == nslot;
   const size_t lds = (size_t)n_acc * a.G.nodes * sizeof(double) + (size_t)n_tiles * a.G.nodes * sizeof(float);
@@ -762,10 +831,10 @@ hipError_t launch_collide_f32(const CollideArgs& a, int nslot, hipStream_t strea
   return hipGetLastError();
 }
 
-hipError_t set_collide_lds_limit(size_t bytes) {
-  // Raising the per-kernel dynamic LDS limit is only needed (and only
-  // accepted) above the runtime's default; a refusal leaves the default, which
-  // the planner's budget then has to respect, so it is not an error here.
+hipError_t set_collide_lds_limit(size_t lds_max, size_t* budget_plain, size_t* budget_learned) {
+  // Each FP32 variant may use what its static LDS leaves of lds_max.  Raising
+  // the per-kernel dynamic limit is only needed (and only accepted) above the
+  // runtime's default; after a refusal the budget is the limit in force.
   const void* fns[16] = {
       (const void*)collide_f32_kernel<true, true, true, false>,   (const void*)collide_f32_kernel<true, false, true, false>,
       (const void*)collide_f32_kernel<false, true, true, false>,  (const void*)collide_f32_kernel<false, false, true, false>,
@@ -775,14 +844,24 @@ hipError_t set_collide_lds_limit(size_t bytes) {
       (const void*)collide_f32_kernel<false, true, true, true>,   (const void*)collide_f32_kernel<false, false, true, true>,
       (const void*)collide_f32_kernel<true, true, false, true>,   (const void*)collide_f32_kernel<true, false, false, true>,
       (const void*)collide_f32_kernel<false, true, false, true>,  (const void*)collide_f32_kernel<false, false, false, true>};
-  for (const void* fn : fns) {
+  size_t budget[2] = {lds_max, lds_max};
+  for (int i = 0; i < 16; ++i) {
     hipFuncAttributes attr;
-    if (hipFuncGetAttributes(&attr, fn) != hipSuccess) return hipGetLastError();
-    if (attr.maxDynamicSharedSizeBytes >= (int)bytes) continue;
-    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) != hipSuccess) {
-      (void)hipGetLastError();
+    if (hipFuncGetAttributes(&attr, fns[i]) != hipSuccess) return hipGetLastError();
+    const size_t stat = attr.sharedSizeBytes;
+    size_t want = lds_max > stat ? lds_max - stat : 0;
+    size_t have = attr.maxDynamicSharedSizeBytes > 0 ? (size_t)attr.maxDynamicSharedSizeBytes : 0;
+    if (have < want) {
+      if (hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)want) == hipSuccess)
+        have = want;
+      else
+        (void)hipGetLastError();
     }
+    size_t& b = budget[i >= 8 ? 1 : 0];
+    b = std::min(b, std::min(have, want));
   }
+  *budget_plain = budget[0];
+  *budget_learned = budget[1];
   return hipSuccess;
 }
 

@@ -23,15 +23,12 @@ qgbe_status hip_fail(hipError_t e, const char* what);
     if (_e != hipSuccess) return ::qgbe::hip_fail(_e, what); \
   } while (0)
 
-// LDS kept free for the collision kernel's static arrays
-constexpr size_t kStaticLds = 3072;
-
 // Channels of the FP32 kernel grouped by their number of deposit slots.
 struct Group {
   int start, count;   // range in the group index array
   int nslot;          // distinct species at positions 2..4
-  int lds_acc;        // FP64 accumulators staged in LDS
-  int lds_tiles;      // FP32 f tiles staged in LDS
+  int lds_acc[2];     // FP64 accumulators staged in LDS  [uniform, learned sampler]
+  int lds_tiles[2];   // FP32 f tiles staged in LDS       [uniform, learned sampler]
 };
 
 // Device buffers of the proposal network (allocated on first use).
@@ -64,6 +61,8 @@ struct qgbe_ctx {
   double* d_f = nullptr;
   double* d_f_next = nullptr;
   float* d_f32 = nullptr;
+  float4* d_f32q = nullptr;        // node quads of d_f32, for tiles read from global memory
+  bool need_quads[2] = {false, false};  // some group reads tiles globally [uniform, learned]
   double* d_mass2 = nullptr;
   double* d_lag = nullptr;
   bool has_lag = false;
@@ -77,6 +76,7 @@ struct qgbe_ctx {
   uint32_t* d_thr = nullptr;
   float* d_mu = nullptr;
   float* d_sigma = nullptr;
+  uint8_t* d_mix_on = nullptr;     // [channels] 1: learned sampler, 0: uniform fallback
   float* d_feat = nullptr;         // [nch * nodes][8] conditioning features
   double* d_mass7 = nullptr;       // cell-averaged masses behind d_feat
   bool table_net = false;          // table comes from the network: rebuilt whenever the masses change
@@ -84,7 +84,7 @@ struct qgbe_ctx {
   qgbe::MlpState mlp;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   size_t ws = 0;
-  size_t lds_bytes = 0;            // dynamic LDS available per workgroup
+  size_t lds_budget[2] = {0, 0};   // dynamic LDS per workgroup [uniform, learned sampler]
 };
 
 namespace qgbe {
@@ -95,6 +95,12 @@ CollideArgs base_args(qgbe_ctx* c, int n_samples, double* A, double* scale, doub
 // Enqueue features, network forward and table construction for the current
 // masses (no allocation, no synchronisation).
 qgbe_status refresh_proposal_table(qgbe_ctx* c);
+// Device buffers of a K-component proposal table (reallocated if K changes).
+qgbe_status install_proposal_table(qgbe_ctx* c, int K);
+// Every channel back on the learned sampler (after a new table or network).
+qgbe_status reset_channel_samplers(qgbe_ctx* c);
+// Device buffers of the conditioning features.
+qgbe_status ensure_proposal_features(qgbe_ctx* c);
 
 template <typename T>
 qgbe_status dev_alloc(qgbe_ctx* c, T** p, size_t n, const char* what) {

@@ -21,6 +21,10 @@ size_t observables_scratch(const Grid& G);
 hipError_t launch_observables(const Grid& G, const double* f, const double* mass2, double* scratch,
                               double* out, hipStream_t st);
 hipError_t launch_to_f32(const double* src, float* dst, size_t n, hipStream_t st);
+// Node quads of the FP32 field: q[i] = (f[i], f[i+1], f[i+oy], f[i+oy+1])
+// within each (species, cell) block, so a trilinear read takes two 16-byte
+// loads; entries on the last z or y layer (never a stencil base) repeat f[i].
+hipError_t launch_f32_quads(const Grid& G, const float* f32, float4* q, hipStream_t st);
 hipError_t launch_fill(double* dst, double v, size_t n, hipStream_t st);
 hipError_t launch_zero_u64(unsigned long long* dst, hipStream_t st);
 

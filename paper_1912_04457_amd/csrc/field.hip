@@ -243,6 +243,16 @@ __global__ void to_f32_kernel(const double* __restrict__ src, float* __restrict_
     dst[i] = (float)src[i];
 }
 
+__global__ void quads_kernel(Grid G, const float* __restrict__ f, float4* __restrict__ q, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const int node = (int)(i % (size_t)G.nodes);
+    const int iz = node % G.np[2], iy = (node / G.np[2]) % G.np[1];
+    const size_t dz = iz + 1 < G.np[2] ? 1 : 0;
+    const size_t dy = iy + 1 < G.np[1] ? (size_t)G.oy : 0;
+    q[i] = make_float4(f[i], f[i + dz], f[i + dy], f[i + dy + dz]);
+  }
+}
+
 __global__ void fill_kernel(double* __restrict__ dst, double v, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     dst[i] = v;
@@ -294,6 +304,12 @@ hipError_t launch_observables(const Grid& G, const double* f, const double* mass
 
 hipError_t launch_to_f32(const double* src, float* dst, size_t n, hipStream_t st) {
   hipLaunchKernelGGL(to_f32_kernel, dim3(grid_for(n)), dim3(kBlock), 0, st, src, dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_f32_quads(const Grid& G, const float* f32, float4* q, hipStream_t st) {
+  const size_t n = (size_t)kSpecies * G.cells * G.nodes;
+  hipLaunchKernelGGL(quads_kernel, dim3(grid_for(n)), dim3(kBlock), 0, st, G, f32, q, n);
   return hipGetLastError();
 }
 

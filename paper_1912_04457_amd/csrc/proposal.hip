@@ -117,7 +117,14 @@ qgbe_status check_weights(qgbe_ctx* c) {
   return QGBE_OK;
 }
 
-qgbe_status install_table_buffers(qgbe_ctx* c, int K) {
+qgbe_status ensure_masses(qgbe_ctx* c) {
+  if (c->masses_valid) return QGBE_OK;
+  return compute_masses(c);
+}
+
+}  // namespace
+
+qgbe_status qgbe::install_proposal_table(qgbe_ctx* c, int K) {
   const size_t rows = (size_t)c->nch * c->G.nodes;
   if (c->d_thr && c->K == K) return QGBE_OK;
   (void)hipFree(c->d_thr);
@@ -127,24 +134,23 @@ qgbe_status install_table_buffers(qgbe_ctx* c, int K) {
   qgbe_status s = dev_alloc(c, &c->d_thr, std::max<size_t>(1, rows * K), "proposal thresholds");
   if (!s) s = dev_alloc(c, &c->d_mu, std::max<size_t>(1, rows * K * 5), "proposal locations");
   if (!s) s = dev_alloc(c, &c->d_sigma, std::max<size_t>(1, rows * K * 5), "proposal scales");
+  if (!s && !c->d_mix_on) s = dev_alloc(c, &c->d_mix_on, std::max(1, c->nch), "channel samplers");
   if (s) return s;
   c->K = K;
   return QGBE_OK;
 }
 
-qgbe_status ensure_feature_buffers(qgbe_ctx* c) {
+qgbe_status qgbe::reset_channel_samplers(qgbe_ctx* c) {
+  HIP_TRY(hipMemsetAsync(c->d_mix_on, 1, std::max(1, c->nch), c->stream), "channel samplers");
+  return QGBE_OK;
+}
+
+qgbe_status qgbe::ensure_proposal_features(qgbe_ctx* c) {
   qgbe_status s = QGBE_OK;
   if (!c->d_feat) s = dev_alloc(c, &c->d_feat, std::max<size_t>(1, (size_t)c->nch * c->G.nodes) * kMlpIn, "features");
   if (!s && !c->d_mass7) s = dev_alloc(c, &c->d_mass7, kSpecies, "mean masses");
   return s;
 }
-
-qgbe_status ensure_masses(qgbe_ctx* c) {
-  if (c->masses_valid) return QGBE_OK;
-  return compute_masses(c);
-}
-
-}  // namespace
 
 // Features of the current (cell-averaged) masses -> network -> table, on the
 // context's stream.  Needs the weights, the table buffers (K = kMixK) and the
@@ -171,9 +177,11 @@ qgbe_status qgbe_set_proposal_table(qgbe_ctx* c, int32_t K, const uint32_t* thr,
   if (!c || !thr || !mu || !sigma) return fail(QGBE_EINVAL, "NULL argument");
   if (K < 1 || K > 16) return fail(QGBE_EINVAL, "K must be in 1..16");
   HIP_TRY(hipSetDevice(c->d.device), "hipSetDevice");
-  qgbe_status s = install_table_buffers(c, K);
+  qgbe_status s = install_proposal_table(c, K);
   if (s) return s;
   c->table_net = false;
+  s = reset_channel_samplers(c);
+  if (s) return s;
   const size_t rows = (size_t)c->nch * c->G.nodes;
   const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   HIP_TRY(hipMemcpyAsync(c->d_thr, thr, rows * K * sizeof(uint32_t), kind, c->stream), "copy thresholds");
@@ -272,7 +280,7 @@ qgbe_status qgbe_proposal_features(qgbe_ctx* c, float* X, int32_t on_device) {
   if (!c || !X) return fail(QGBE_EINVAL, "NULL argument");
   HIP_TRY(hipSetDevice(c->d.device), "hipSetDevice");
   qgbe_status s = ensure_masses(c);
-  if (!s) s = ensure_feature_buffers(c);
+  if (!s) s = ensure_proposal_features(c);
   if (s) return s;
   const size_t rows = (size_t)c->nch * c->G.nodes;
   HIP_TRY(launch_features(c->G, c->d_chans, c->nch, c->d_mass2, c->d_mass7, c->d_feat, c->stream), "features");
@@ -314,17 +322,99 @@ qgbe_status qgbe_proposal_build_table(qgbe_ctx* c, float alpha) {
   if (s) return s;
   HIP_TRY(hipSetDevice(c->d.device), "hipSetDevice");
   s = ensure_masses(c);
-  if (!s) s = install_table_buffers(c, kMixK);
-  if (!s) s = ensure_feature_buffers(c);
+  if (!s) s = install_proposal_table(c, kMixK);
+  if (!s) s = ensure_proposal_features(c);
   if (s) return s;
   c->table_alpha = alpha;
   c->table_net = true;
-  s = refresh_proposal_table(c);
+  s = reset_channel_samplers(c);
+  if (!s) s = refresh_proposal_table(c);
   if (s) {
     c->table_net = false;
     return s;
   }
   HIP_TRY(hipStreamSynchronize(c->stream), "build proposal table");
+  return QGBE_OK;
+}
+
+qgbe_status qgbe_set_channel_samplers(qgbe_ctx* c, const uint8_t* use_learned) {
+  if (!c || !use_learned) return fail(QGBE_EINVAL, "NULL argument");
+  if (!c->K) return fail(QGBE_ESTATE, "no proposal table installed");
+  std::vector<uint8_t> v(std::max(1, c->nch), 1);
+  for (int i = 0; i < c->nch; ++i) {
+    if (use_learned[i] > 1) return fail(QGBE_EINVAL, "channel sampler flags must be 0 or 1");
+    v[i] = use_learned[i];
+  }
+  HIP_TRY(hipSetDevice(c->d.device), "hipSetDevice");
+  HIP_TRY(hipMemcpyAsync(c->d_mix_on, v.data(), v.size(), hipMemcpyHostToDevice, c->stream), "copy flags");
+  HIP_TRY(hipStreamSynchronize(c->stream), "synchronise");
+  return QGBE_OK;
+}
+
+qgbe_status qgbe_get_channel_samplers(qgbe_ctx* c, uint8_t* use_learned) {
+  if (!c || !use_learned) return fail(QGBE_EINVAL, "NULL argument");
+  if (!c->K) return fail(QGBE_ESTATE, "no proposal table installed");
+  HIP_TRY(hipSetDevice(c->d.device), "hipSetDevice");
+  HIP_TRY(hipMemcpyAsync(use_learned, c->d_mix_on, c->nch, hipMemcpyDeviceToHost, c->stream), "copy flags");
+  HIP_TRY(hipStreamSynchronize(c->stream), "synchronise");
+  return QGBE_OK;
+}
+
+qgbe_status qgbe_proposal_judge(qgbe_ctx* c, int32_t n_pilot, int32_t n_reps, uint8_t* use_learned,
+                                double* ratio) {
+  if (!c) return fail(QGBE_EINVAL, "NULL context");
+  if (n_pilot < 1 || n_reps < 2) return fail(QGBE_EINVAL, "n_pilot >= 1 and n_reps >= 2 required");
+  if (!c->K) return fail(QGBE_ESTATE, "no proposal table installed");
+  HIP_TRY(hipSetDevice(c->d.device), "hipSetDevice");
+  const size_t n_items = (size_t)c->G.cells * c->nch * c->G.nodes;
+  if (n_items == 0) return QGBE_OK;
+  double* d_items = nullptr;
+  HIP_TRY(hipMalloc(&d_items, n_items * sizeof(double)), "pilot scratch");
+  std::vector<double> h(n_items), sum[2], sq[2];
+  double t_ms[2] = {0.0, 0.0};
+  const uint32_t saved_step = c->step;
+  qgbe_status s = reset_channel_samplers(c);
+  for (int l = 0; l < 2 && !s; ++l) {
+    sum[l].assign(n_items, 0.0);
+    sq[l].assign(n_items, 0.0);
+    for (int r = 0; r < n_reps && !s; ++r) {
+      // pilot draws use their own key range, apart from the run's steps
+      c->step = 0xF0000000u + (uint32_t)r;
+      qgbe_collide_extras ex{nullptr, d_items, 1};
+      qgbe_stats st;
+      s = qgbe_collision_term_ex(c, n_pilot, l ? QGBE_SAMPLER_LEARNED : QGBE_SAMPLER_UNIFORM, c->d_A, 1, &ex, &st);
+      if (s) break;
+      t_ms[l] += st.t_collide_ms;
+      hipError_t e = hipMemcpy(h.data(), d_items, n_items * sizeof(double), hipMemcpyDeviceToHost);
+      if (e != hipSuccess) { s = hip_fail(e, "copy pilot sums"); break; }
+      for (size_t i = 0; i < n_items; ++i) {
+        sum[l][i] += h[i];
+        sq[l][i] += h[i] * h[i];
+      }
+    }
+  }
+  c->step = saved_step;
+  (void)hipFree(d_items);
+  if (s) return s;
+  // per channel: summed variance of the item estimates x total pilot time
+  std::vector<uint8_t> flags(std::max(1, c->nch), 1);
+  const double R = n_reps;
+  for (int ci = 0; ci < c->nch; ++ci) {
+    double var[2] = {0.0, 0.0};
+    for (int l = 0; l < 2; ++l)
+      for (int x = 0; x < c->G.cells; ++x)
+        for (int p = 0; p < c->G.nodes; ++p) {
+          const size_t i = ((size_t)x * c->nch + ci) * c->G.nodes + p;
+          const double m = sum[l][i] / R;
+          var[l] += std::max(0.0, (sq[l][i] - R * m * m) / (R - 1.0));
+        }
+    const double cost_u = var[0] * t_ms[0], cost_l = var[1] * t_ms[1];
+    flags[ci] = (cost_u > 0.0 && cost_l < cost_u) ? 1 : 0;
+    if (ratio) ratio[ci] = cost_u > 0.0 ? cost_l / cost_u : (cost_l > 0.0 ? INFINITY : 1.0);
+  }
+  HIP_TRY(hipMemcpyAsync(c->d_mix_on, flags.data(), flags.size(), hipMemcpyHostToDevice, c->stream), "copy flags");
+  HIP_TRY(hipStreamSynchronize(c->stream), "synchronise");
+  if (use_learned) std::memcpy(use_learned, flags.data(), c->nch);
   return QGBE_OK;
 }
 

@@ -31,6 +31,8 @@ EXPORTS = (
     "qgbe_channel_table", "qgbe_philox4x32_10", "qgbe_proposal_set_weights",
     "qgbe_proposal_get_weights", "qgbe_mlp_forward", "qgbe_mlp_loss_grad", "qgbe_proposal_features",
     "qgbe_record_samples", "qgbe_train_proposal", "qgbe_proposal_build_table", "qgbe_get_proposal_table",
+    "qgbe_checkpoint", "qgbe_restore", "qgbe_set_channel_samplers", "qgbe_get_channel_samplers",
+    "qgbe_proposal_judge",
 )
 MLP_PARAMS = 29016
 MLP_BATCH = 16384
@@ -120,6 +122,11 @@ def lib() -> C.CDLL:
             "qgbe_train_proposal": (i32, [p, p, C.c_int64, p, p, i32]),
             "qgbe_proposal_build_table": (i32, [p, C.c_float]),
             "qgbe_get_proposal_table": (i32, [p, p, p, p, p]),
+            "qgbe_checkpoint": (i32, [p, p, p]),
+            "qgbe_restore": (i32, [p, p, C.c_size_t]),
+            "qgbe_set_channel_samplers": (i32, [p, p]),
+            "qgbe_get_channel_samplers": (i32, [p, p]),
+            "qgbe_proposal_judge": (i32, [p, i32, i32, p, p]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -319,6 +326,40 @@ def qgbe_get_proposal_table(ctx, rows: int):
     _check(lib().qgbe_get_proposal_table(ctx, C.byref(K), thr.ctypes.data_as(C.c_void_p),
                                          mu.ctypes.data_as(C.c_void_p), sg.ctypes.data_as(C.c_void_p)))
     return thr, mu, sg
+
+
+def qgbe_checkpoint(ctx) -> bytes:
+    """The context's state as a byte string (see qgbe_restore)."""
+    n = C.c_size_t(0)
+    _check(lib().qgbe_checkpoint(ctx, None, C.byref(n)))
+    buf = C.create_string_buffer(n.value)
+    _check(lib().qgbe_checkpoint(ctx, buf, C.byref(n)))
+    return buf.raw[:n.value]
+
+
+def qgbe_restore(ctx, state: bytes) -> None:
+    buf = C.create_string_buffer(state, len(state))
+    _check(lib().qgbe_restore(ctx, buf, len(state)))
+
+
+def qgbe_set_channel_samplers(ctx, use_learned) -> None:
+    v = np.ascontiguousarray(use_learned, dtype=np.uint8)
+    _check(lib().qgbe_set_channel_samplers(ctx, v.ctypes.data_as(C.c_void_p)))
+
+
+def qgbe_get_channel_samplers(ctx, n_channels: int) -> np.ndarray:
+    v = np.zeros(n_channels, dtype=np.uint8)
+    _check(lib().qgbe_get_channel_samplers(ctx, v.ctypes.data_as(C.c_void_p)))
+    return v
+
+
+def qgbe_proposal_judge(ctx, n_pilot: int, n_reps: int, n_channels: int):
+    """Run the fallback judge; returns (use_learned [channels] uint8, ratio [channels])."""
+    flags = np.zeros(n_channels, dtype=np.uint8)
+    ratio = np.zeros(n_channels)
+    _check(lib().qgbe_proposal_judge(ctx, n_pilot, n_reps, flags.ctypes.data_as(C.c_void_p),
+                                     ratio.ctypes.data_as(C.c_void_p)))
+    return flags, ratio
 
 
 def qgbe_channel_table(species_mask: int, row_mask: int = 0x7F):

@@ -1,0 +1,86 @@
+"""Checkpoint / restore of a context's state (f, step index, lagged masses,
+learned proposal) through the C ABI."""
+import numpy as np
+import pytest
+
+from paper_1912_04457_amd import qgbe
+from paper_1912_04457_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+WL = W.Workload("qg7_2cells_6cube", (2, 1, 1), (6, 6, 6), (3.0, 3.0, 3.0), (2.0, 2.0, 2.0),
+                0x7F, 64, "f64", 1, 0.01)
+
+
+def _case(name):
+    print(f"\n[gpu case] {name}", flush=True)
+
+
+def _solver(**kw):
+    return qgbe.Solver(n_x=WL.n_x, n_p=WL.n_p, x_half=WL.x_half, p_half=WL.p_half,
+                       species_mask=WL.species_mask, alpha_s=WL.alpha_s, seed=0x5EED2019, **kw)
+
+
+@pytest.mark.parametrize("precision,tol", [(qgbe.FP64, 1e-12), (qgbe.FP32, 1e-6)])
+def test_resume_continues_the_run(precision, tol):
+    """Steps 3-4 from a restored checkpoint equal steps 3-4 of the original run
+    (same samples; FP64 atomics may add in another order, which in FP32 mode
+    can move an FP32 rounding of f by one unit)."""
+    _case(f"checkpoint resume precision={precision}")
+    f0 = W.random_f(41, WL.cells, WL.nodes) * 0.4
+    with _solver(precision=precision) as a:
+        a.set_f(f0)
+        a.step(0.01, WL.n_samples, n_steps=2)
+        state = qgbe.qgbe_checkpoint(a.ctx)
+        a.step(0.01, WL.n_samples, n_steps=2)
+        f_a = a.get_f()
+        step_a = qgbe.qgbe_get_step_index(a.ctx)
+    with _solver(precision=precision) as b:
+        qgbe.qgbe_restore(b.ctx, state)
+        assert qgbe.qgbe_get_step_index(b.ctx) == 2
+        b.step(0.01, WL.n_samples, n_steps=2)
+        f_b = b.get_f()
+        assert qgbe.qgbe_get_step_index(b.ctx) == step_a
+    scale = np.abs(f_a).max()
+    assert np.abs(f_a - f_b).max() <= tol * scale
+
+
+def test_proposal_state_round_trips():
+    _case("checkpoint proposal")
+    f0 = W.random_f(42, WL.cells, WL.nodes) * 0.4
+    w = W.random_mlp_params(9, head_scale=1.0)
+    rows = 70 * WL.nodes
+    with _solver(precision=qgbe.FP32) as a:
+        a.set_f(f0)
+        qgbe.qgbe_proposal_set_weights(a.ctx, w)
+        qgbe.qgbe_proposal_build_table(a.ctx, 0.1)
+        tab_a = qgbe.qgbe_get_proposal_table(a.ctx, rows)
+        A_a = a.collision(64, sampler=qgbe.SAMPLER_LEARNED)[0]
+        state = qgbe.qgbe_checkpoint(a.ctx)
+    with _solver(precision=qgbe.FP32) as b:
+        qgbe.qgbe_restore(b.ctx, state)
+        assert np.array_equal(qgbe.qgbe_proposal_get_weights(b.ctx), w)
+        tab_b = qgbe.qgbe_get_proposal_table(b.ctx, rows)
+        for x, y in zip(tab_a, tab_b):
+            assert np.array_equal(x, y)
+        A_b = b.collision(64, sampler=qgbe.SAMPLER_LEARNED)[0]
+    assert np.abs(A_a - A_b).max() <= 1e-12 * np.abs(A_a).max()
+
+
+def test_restore_rejects_foreign_or_damaged_buffers():
+    _case("checkpoint errors")
+    with _solver() as a:
+        a.set_f(W.random_f(43, WL.cells, WL.nodes) * 0.4)
+        state = qgbe.qgbe_checkpoint(a.ctx)
+        with pytest.raises(qgbe.QgbeError):
+            qgbe.qgbe_restore(a.ctx, state[:len(state) // 2])
+        with pytest.raises(qgbe.QgbeError):
+            qgbe.qgbe_restore(a.ctx, b"XXXXXXXX" + state[8:])
+    other = qgbe.Solver(n_x=(1, 1, 1), n_p=WL.n_p, x_half=WL.x_half, p_half=WL.p_half,
+                        species_mask=WL.species_mask, alpha_s=WL.alpha_s, seed=0x5EED2019)
+    with other:
+        with pytest.raises(qgbe.QgbeError):
+            qgbe.qgbe_restore(other.ctx, state)
+    with _solver(precision=qgbe.FP32) as c:
+        with pytest.raises(qgbe.QgbeError):
+            qgbe.qgbe_restore(c.ctx, state)

@@ -154,6 +154,71 @@ def test_learned_collision_parity(O, precision, tol):
         assert abs(A[:, cell].sum()) <= 1e-13 * S_ref[:, cell].sum()
 
 
+def test_learned_config3_layout_fp32(O):
+    """20^3, 7 species: the learned variant's LDS plan reads some f tiles from
+    global memory (node quads) and deposits one slot with global atomics."""
+    _case("learned C3 layout fp32 N=8")
+    wl = W.C3
+    f = W.initial_f(wl)
+    g = O.Grid(n_x=wl.n_x, n_p=wl.n_p, x_half=wl.x_half, p_half=wl.p_half, species_mask=wl.species_mask)
+    rows = len(O.channels(g)) * wl.nodes
+    thr, mu, sg = W.random_mog_table(39, rows, K=8, alpha=0.1, mu_scale=1.0, log_sigma=(-1.0, 0.5))
+    with qgbe.Solver(**_kw(wl), precision=qgbe.FP32) as s:
+        s.set_f(f)
+        qgbe.qgbe_set_proposal_table(s.ctx, thr, mu, sg)
+        A, _, _, _ = s.collision(8, sampler=qgbe.SAMPLER_LEARNED)
+    m = O.masses(g, f)
+    A_ref, S_ref, _ = O.collision_learned(g, f, m, SEED, 0, 8, thr, mu, sg)
+    err = np.abs(A - A_ref)
+    assert np.all(err <= 1e-4 * S_ref + 1e-300), float((err / np.maximum(S_ref, 1e-300)).max())
+    assert abs(A.sum()) <= 1e-13 * S_ref.sum()
+
+
+@pytest.mark.parametrize("precision,tol", [(qgbe.FP64, 1e-10), (qgbe.FP32, 1e-4)])
+def test_channel_fallback_parity(O, precision, tol):
+    """Half of the channels fall back to the uniform sampler."""
+    _case(f"fallback parity precision={precision}")
+    wl = SMALL_7
+    f = W.random_f(36, wl.cells, wl.nodes)
+    g = O.Grid(n_x=wl.n_x, n_p=wl.n_p, x_half=wl.x_half, p_half=wl.p_half, species_mask=wl.species_mask)
+    nch = len(O.channels(g))
+    thr, mu, sg = W.random_mog_table(37, nch * wl.nodes, K=8, alpha=0.1, mu_scale=1.0, log_sigma=(-1.0, 0.5))
+    flags = (np.arange(nch) % 2).astype(np.uint8)
+    with qgbe.Solver(**_kw(wl), precision=precision) as s:
+        s.set_f(f)
+        qgbe.qgbe_set_step_index(s.ctx, 3)
+        qgbe.qgbe_set_proposal_table(s.ctx, thr, mu, sg)
+        assert np.all(qgbe.qgbe_get_channel_samplers(s.ctx, nch) == 1)
+        qgbe.qgbe_set_channel_samplers(s.ctx, flags)
+        assert np.array_equal(qgbe.qgbe_get_channel_samplers(s.ctx, nch), flags)
+        A, _, _, _ = s.collision(100, sampler=qgbe.SAMPLER_LEARNED)
+    m = O.masses(g, f)
+    A_ref, S_ref, _ = O.collision_learned(g, f, m, SEED, 3, 100, thr, mu, sg, chan_learned=flags)
+    err = np.abs(A - A_ref)
+    assert np.all(err <= tol * S_ref + 1e-300), float((err / np.maximum(S_ref, 1e-300)).max())
+
+
+def test_judge_rejects_a_poor_proposal():
+    """A table of narrow components far from the integrand's mass, with a
+    small defensive share, has a much larger variance than the uniform
+    sampler: the judge sends (nearly) every channel back to uniform."""
+    _case("judge poor table")
+    wl = W.C3.scaled(n_p=(6, 6, 6))
+    with qgbe.Solver(**_kw(wl), precision=qgbe.FP32) as s:
+        s.set_f(W.initial_f(wl))
+        nch = s.n_channels
+        thr, mu, sg = W.random_mog_table(38, nch * wl.nodes, K=8, alpha=0.02, mu_scale=3.0,
+                                         log_sigma=(-4.0, -3.0))
+        qgbe.qgbe_set_proposal_table(s.ctx, thr, mu, sg)
+        step0 = qgbe.qgbe_get_step_index(s.ctx)
+        flags, ratio = qgbe.qgbe_proposal_judge(s.ctx, 64, 4, nch)
+        assert qgbe.qgbe_get_step_index(s.ctx) == step0
+        assert np.array_equal(qgbe.qgbe_get_channel_samplers(s.ctx, nch), flags)
+    print(f"[judge] learned kept on {int(flags.sum())} of {nch} channels; median ratio {np.median(ratio):.3g}")
+    assert flags.mean() <= 0.2
+    assert np.all((ratio < 1.0) == (flags == 1))
+
+
 def _mc_error(samples):
     mean = samples.mean(0)
     var = samples.var(0, ddof=1)
@@ -184,10 +249,18 @@ def test_trained_proposal_unbiased_and_better():
             qgbe.qgbe_set_step_index(s.ctx, 100 + r)
             plain.append(s.collision(N)[0])
             learned.append(s.collision(N, sampler=qgbe.SAMPLER_LEARNED)[0])
-    plain, learned = np.array(plain), np.array(learned)
-    e_plain, e_learned = _mc_error(plain), _mc_error(learned)
-    print(f"[train] MC error plain {e_plain:.4f} learned {e_learned:.4f}", flush=True)
-    assert e_learned < e_plain
+        nch = s.n_channels
+        flags, ratio = qgbe.qgbe_proposal_judge(s.ctx, 64, 4, nch)
+        print(f"[train] judge keeps the learned sampler on {int(flags.sum())} of {nch} channels", flush=True)
+        judged = []
+        for r in range(R):
+            qgbe.qgbe_set_step_index(s.ctx, 100 + r)
+            judged.append(s.collision(N, sampler=qgbe.SAMPLER_LEARNED)[0])
+    plain, learned, judged = np.array(plain), np.array(learned), np.array(judged)
+    e_plain, e_learned, e_judged = _mc_error(plain), _mc_error(learned), _mc_error(judged)
+    print(f"[train] MC error plain {e_plain:.4f} learned {e_learned:.4f} judged {e_judged:.4f}", flush=True)
+    assert e_learned < e_plain and e_judged < e_plain
+    assert flags.mean() >= 0.5
     diff = learned.mean(0) - plain.mean(0)
     se = np.sqrt(learned.var(0, ddof=1) / R + plain.var(0, ddof=1) / R)
     keep = se > 0

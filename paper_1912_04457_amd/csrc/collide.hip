@@ -90,6 +90,57 @@ __device__ __forceinline__ void sincos_2pi(double u, double& sn, double& cs) {
   cs = ((k + 1) & 2) ? -b : b;
 }
 
+// e^x: x = k ln2 + r with |r| <= ln2/2 (ln2 split so k*ln2_hi is exact for
+// |k| < 2^11), the Taylor series of e^r to r^13 (remainder < 5e-18), times
+// 2^k.  Overflows to inf and underflows to 0 like exp.
+__device__ __forceinline__ double exp64(double x) {
+  const double k = rint(x * 1.4426950408889634);
+  double r = fma(-k, 0.6931471805598903, x);
+  r = fma(-k, 5.497923018708371e-14, r);
+  double p = 1.6059043836821613e-10;
+  p = fma(p, r, 2.08767569878681e-09);
+  p = fma(p, r, 2.505210838544172e-08);
+  p = fma(p, r, 2.755731922398589e-07);
+  p = fma(p, r, 2.7557319223985893e-06);
+  p = fma(p, r, 2.48015873015873e-05);
+  p = fma(p, r, 0.0001984126984126984);
+  p = fma(p, r, 0.001388888888888889);
+  p = fma(p, r, 0.008333333333333333);
+  p = fma(p, r, 0.041666666666666664);
+  p = fma(p, r, 0.16666666666666666);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return ldexp(p, (int)k);
+}
+
+// ln a for finite a > 0: a = m 2^e with m in [1/sqrt2, sqrt2), ln m =
+// 2 atanh(s), s = (m-1)/(m+1), |s| <= 0.172, by its series to s^21
+// (remainder < 1e-17).
+__device__ __forceinline__ double log64(double a) {
+  int e;
+  double m = frexp(a, &e);
+  if (m < 0.7071067811865476) {
+    m *= 2.0;
+    e -= 1;
+  }
+  const double s = (m - 1.0) * rcp64(m + 1.0);
+  const double s2 = s * s;
+  double p = 0.047619047619047616;
+  p = fma(p, s2, 0.05263157894736842);
+  p = fma(p, s2, 0.058823529411764705);
+  p = fma(p, s2, 0.06666666666666667);
+  p = fma(p, s2, 0.07692307692307693);
+  p = fma(p, s2, 0.09090909090909091);
+  p = fma(p, s2, 0.1111111111111111);
+  p = fma(p, s2, 0.14285714285714285);
+  p = fma(p, s2, 0.2);
+  p = fma(p, s2, 0.3333333333333333);
+  p = fma(p, s2, 1.0);
+  const double de = (double)e;
+  return fma(de, 0.6931471805598903, fma(de, 5.497923018708371e-14, 2.0 * s * p));
+}
+
 __device__ __forceinline__ double sqrt64(double x) { return x > 0.0 ? x * rsqrt64(x) : 0.0; }
 
 template <typename R>
@@ -299,7 +350,7 @@ __device__ __forceinline__ void mix_draw(const uint32_t x[8], const uint32_t* __
   if (x[0] < thr[0]) {
     for (int d = 0; d < 5; ++d) {
       u[d] = unif23(x[1 + d] >> 9);
-      y[d] = log(u[d] / (1.0 - u[d]));
+      y[d] = log64(u[d] * rcp64(1.0 - u[d]));
     }
     return;
   }
@@ -308,15 +359,54 @@ __device__ __forceinline__ void mix_draw(const uint32_t x[8], const uint32_t* __
   double z[6];
   for (int pr = 0; pr < 3; ++pr) {
     const double a1 = unif23(x[1 + 2 * pr] >> 9), a2 = unif23(x[2 + 2 * pr] >> 9);
-    const double r = sqrt(-2.0 * log(a1));
+    const double r = sqrt64(-2.0 * log64(a1));
     double sn, cs;
-    sincospi(2.0 * a2, &sn, &cs);
+    sincos_2pi(a2, sn, cs);
     z[2 * pr] = r * cs;
     z[2 * pr + 1] = r * sn;
   }
   for (int d = 0; d < 5; ++d) {
     y[d] = (double)mu[k * 5 + d] + (double)sg[k * 5 + d] * z[d];
-    u[d] = 1.0 / (1.0 + exp(-y[d]));
+    u[d] = rcp64(1.0 + exp64(-y[d]));
+  }
+}
+
+// Per-item constants of the FP32 sampler, one row per wave in LDS: mu (40),
+// 1/sigma (40), log pi_k - sum_d log sigma_kd - 5/2 log 2 pi (8), alpha,
+// sigma (40).
+constexpr int kMixSigma = 89;
+constexpr int kMixRow = kMixSigma + 40;
+
+// The same draw for the FP32 kernel: component parameters from the wave's
+// LDS row (see mix_prepare_f32), thresholds from the (wave-uniform) table
+// row; u in FP64 (it feeds the FP64 geometry), y in FP32 (it feeds only the
+// FP32 density).
+__device__ __forceinline__ void mix_draw_row(const uint32_t x[8], const uint32_t* __restrict__ thr, const float* row,
+                                             int K, double u[5], float y[5]) {
+  if (x[0] < thr[0]) {
+    for (int d = 0; d < 5; ++d) {
+      const uint32_t v = x[1 + d] >> 9;
+      u[d] = unif23(v);
+      const float uf = ((float)v + 0.5f) * (1.0f / 8388608.0f);  // = u[d] exactly
+      y[d] = __logf(uf) - __logf(1.0f - uf);
+    }
+    return;
+  }
+  int k = 0;
+  for (int j = 1; j < K; ++j) k = x[0] >= thr[j] ? j : k;
+  double z[6];
+  for (int pr = 0; pr < 3; ++pr) {
+    const double a1 = unif23(x[1 + 2 * pr] >> 9), a2 = unif23(x[2 + 2 * pr] >> 9);
+    const double r = sqrt64(-2.0 * log64(a1));
+    double sn, cs;
+    sincos_2pi(a2, sn, cs);
+    z[2 * pr] = r * cs;
+    z[2 * pr + 1] = r * sn;
+  }
+  for (int d = 0; d < 5; ++d) {
+    const double yd = (double)row[k * 5 + d] + (double)row[kMixSigma + k * 5 + d] * z[d];
+    u[d] = rcp64(1.0 + exp64(-yd));
+    y[d] = (float)yd;
   }
 }
 
@@ -352,15 +442,13 @@ __device__ __forceinline__ double mix_density_f64(const uint32_t* thr, const flo
   return (double)thr[0] / kTwo32 + exp(lq);
 }
 
-// Per-item constants of the FP32 density: mu (40), 1/sigma (40), log pi_k -
-// sum_d log sigma_kd - 5/2 log 2 pi (8), alpha.
-constexpr int kMixRow = 90;
 
 __device__ __forceinline__ void mix_prepare_f32(const uint32_t* thr, const float* mu, const float* sg, int K,
                                                 float* row, int lane) {
   for (int i = lane; i < K * 5; i += kWave) {
     row[i] = mu[i];
     row[40 + i] = 1.0f / sg[i];
+    row[kMixSigma + i] = sg[i];
   }
   if (lane < K) {
     const double hi = lane + 1 < K ? (double)thr[lane + 1] : kTwo32;
@@ -372,9 +460,7 @@ __device__ __forceinline__ void mix_prepare_f32(const uint32_t* thr, const float
   if (lane == 0) row[88] = (float)((double)thr[0] / kTwo32);
 }
 
-__device__ __forceinline__ float mix_density_f32(const float* row, int K, const double y[5]) {
-  float yf[5];
-  for (int d = 0; d < 5; ++d) yf[d] = (float)y[d];
+__device__ __forceinline__ float mix_density_f32(const float* row, int K, const float yf[5]) {
   float lk[16];
   float mx = -1e30f;
   for (int k = 0; k < K; ++k) {
@@ -389,7 +475,11 @@ __device__ __forceinline__ float mix_density_f32(const float* row, int K, const 
   float acc = 0.f;
   for (int k = 0; k < K; ++k) acc += __expf(lk[k] - mx);
   float lq = mx + __logf(acc);
-  for (int d = 0; d < 5; ++d) lq -= log_u1mu<float>(yf[d]);
+  // log(u (1 - u)) = -|y| - 2 log(1 + e^-|y|)
+  for (int d = 0; d < 5; ++d) {
+    const float a = fabsf(yf[d]);
+    lq += a + 2.0f * __logf(1.0f + __expf(-a));
+  }
   return row[88] + __expf(lq);
 }
 
@@ -679,9 +769,8 @@ __global__ __launch_bounds__(f32_threads(kLearned)) void collide_f32_kernel(Coll
         uint32_t y0 = (uint32_t)s, y1 = (uint32_t)p1_lin, y2 = (uint32_t)cell, y3 = ((uint32_t)ch.code << 8) | 1u;
         philox4x32_10(y0, y1, y2, y3, A.key0, A.key1);
         const uint32_t xw[8] = {x0, x1, x2, x3, y0, y1, y2, y3};
-        double yl[5];
-        mix_draw(xw, A.mix_thr + mrow * A.mix_K, A.mix_mu + mrow * A.mix_K * 5, A.mix_sigma + mrow * A.mix_K * 5,
-                 A.mix_K, u, yl);
+        float yl[5];
+        mix_draw_row(xw, A.mix_thr + mrow * A.mix_K, mix_rows[wid], A.mix_K, u, yl);
         inv_q = 1.0f / mix_density_f32(mix_rows[wid], A.mix_K, yl);
       } else {
         five_uniforms(x0, x1, x2, x3, u);

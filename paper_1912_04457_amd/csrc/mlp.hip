@@ -208,6 +208,133 @@ __global__ void table_kernel(const float* __restrict__ Y, int rows, float alpha,
   }
 }
 
+// Inference straight to the proposal table: each wave takes 16-row blocks of
+// X through the network (layer 1 on the vector ALUs, K = 8; layers 2 and 3 on
+// the matrix cores with the block's weights staged in LDS, transposed so the
+// K index is contiguous) and turns its head rows into table rows; the
+// activations never leave LDS.  Numerics as the staged GEMMs: BF16 inputs,
+// weights and hidden activations, FP32 accumulation and head.
+constexpr int kInfWaves = 4;
+constexpr int kHPad = kMlpHidden + 8;     // row stride of the hidden tile (bank spread)
+constexpr int kOutPad = 96;               // head columns rounded up to MFMA tiles
+constexpr int kYPad = kMlpOut + 4;
+
+__global__ __launch_bounds__(kInfWaves * 64) void mlp_table_kernel(const float* __restrict__ X, int rows,
+                                                                    const __bf16* __restrict__ pb,
+                                                                    const float* __restrict__ P, float alpha,
+                                                                    uint32_t* __restrict__ thr, float* __restrict__ mu,
+                                                                    float* __restrict__ sigma) {
+  __shared__ __bf16 W2t[kMlpHidden][kHPad];   // [n][k]
+  __shared__ __bf16 W3t[kOutPad][kHPad];      // [n][k], rows >= 88 zero
+  __shared__ float W1s[kMlpIn][kMlpHidden];
+  __shared__ float bias[2 * kMlpHidden + kMlpOut];
+  __shared__ float Xs[kInfWaves][16][kMlpIn];
+  __shared__ __bf16 H[kInfWaves][16][kHPad];
+  __shared__ float Ys[kInfWaves][16][kYPad];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  for (int e = tid; e < kMlpHidden * kMlpHidden; e += blockDim.x) {
+    const int k = e / kMlpHidden, n = e % kMlpHidden;
+    W2t[n][k] = pb[kOffW2 + e];
+  }
+  for (int e = tid; e < kOutPad * kMlpHidden; e += blockDim.x) {
+    const int n = e / kMlpHidden, k = e % kMlpHidden;
+    W3t[n][k] = n < kMlpOut ? pb[kOffW3 + k * kMlpOut + n] : (__bf16)0.0f;
+  }
+  for (int e = tid; e < kMlpIn * kMlpHidden; e += blockDim.x) W1s[e / kMlpHidden][e % kMlpHidden] = (float)pb[kOffW1 + e];
+  for (int e = tid; e < kMlpHidden; e += blockDim.x) {
+    bias[e] = P[kOffB1 + e];
+    bias[kMlpHidden + e] = P[kOffB2 + e];
+  }
+  for (int e = tid; e < kMlpOut; e += blockDim.x) bias[2 * kMlpHidden + e] = P[kOffB3 + e];
+  __syncthreads();
+  const int n_blocks = (rows + 15) / 16;
+  const int r16 = lane & 15, kq = (lane >> 4) * 8, rq = (lane >> 4) * 4;
+  for (int t = blockIdx.x * kInfWaves + w; t < n_blocks; t += gridDim.x * kInfWaves) {
+    const int row0 = t * 16;
+    // inputs, rounded to BF16 like the staged path
+    for (int e = lane; e < 16 * kMlpIn; e += 64) {
+      const int r = e / kMlpIn, c = e % kMlpIn;
+      Xs[w][r][c] = row0 + r < rows ? (float)(__bf16)X[(size_t)(row0 + r) * kMlpIn + c] : 0.0f;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // layer 1: lane owns columns lane and lane + 64
+    for (int h = 0; h < 2; ++h) {
+      const int n = lane + 64 * h;
+      float wcol[kMlpIn];
+      for (int k = 0; k < kMlpIn; ++k) wcol[k] = W1s[k][n];
+      for (int r = 0; r < 16; ++r) {
+        float z = bias[n];
+        for (int k = 0; k < kMlpIn; ++k) z = fmaf(Xs[w][r][k], wcol[k], z);
+        H[w][r][n] = (__bf16)silu_f(z);
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // layers 2 and 3 on the matrix cores
+    for (int layer = 0; layer < 2; ++layer) {
+      bf16x8 a[kMlpHidden / kKStep];
+      for (int ks = 0; ks < kMlpHidden / kKStep; ++ks)
+        for (int q = 0; q < 8; ++q) a[ks][q] = H[w][r16][ks * kKStep + kq + q];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const int n_tiles = layer == 0 ? kMlpHidden / 16 : kOutPad / 16;
+      for (int j = 0; j < n_tiles; ++j) {
+        floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int ks = 0; ks < kMlpHidden / kKStep; ++ks) {
+          bf16x8 b;
+          for (int q = 0; q < 8; ++q)
+            b[q] = layer == 0 ? W2t[j * 16 + r16][ks * kKStep + kq + q] : W3t[j * 16 + r16][ks * kKStep + kq + q];
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[ks], b, acc, 0, 0, 0);
+        }
+        const int c = j * 16 + r16;
+        for (int q = 0; q < 4; ++q) {
+          if (layer == 0) {
+            H[w][rq + q][c] = (__bf16)silu_f(acc[q] + bias[kMlpHidden + c]);
+          } else if (c < kMlpOut) {
+            Ys[w][rq + q][c] = acc[q] + bias[2 * kMlpHidden + c];
+          }
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+    // head -> table: four lanes per row; lane part 0 also forms the thresholds
+    const int r = lane >> 2, part = lane & 3;
+    const int row = row0 + r;
+    if (row < rows) {
+      const float* h = Ys[w][r];
+      if (part == 0) {
+        double mx = -1e300;
+        for (int k = 0; k < kMixK; ++k) mx = fmax(mx, (double)h[k]);
+        double e[kMixK], se = 0.0;
+        for (int k = 0; k < kMixK; ++k) { e[k] = exp((double)h[k] - mx); se += e[k]; }
+        double cum = 0.0;
+        for (int k = 0; k < kMixK; ++k) {
+          const double lo = (double)alpha + (1.0 - (double)alpha) * cum;
+          double tt = floor(lo * 4294967296.0);
+          tt = tt > 4294967295.0 ? 4294967295.0 : tt;
+          thr[(size_t)row * kMixK + k] = (uint32_t)tt;
+          cum += e[k] / se;
+        }
+      }
+      for (int k = part; k < kMixK; k += 4)
+        for (int d = 0; d < kMixD; ++d) {
+          mu[((size_t)row * kMixK + k) * kMixD + d] = h[kMixK + k * kMixD + d];
+          const float lr = h[kMixK + kMixK * kMixD + k * kMixD + d];
+          sigma[((size_t)row * kMixK + k) * kMixD + d] = expf(fminf(fmaxf(lr, kLsMin), kLsMax));
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+}
+
 // Per-species thermal mass squared averaged over the cells (one workgroup per
 // species, fixed summation order).
 __global__ void mass_mean_kernel(Grid G, const double* __restrict__ mass2, double* __restrict__ mean) {
@@ -323,6 +450,16 @@ hipError_t launch_features(const Grid& G, const Channel* chans, int nch, const d
   const int rows = nch * G.nodes;
   if (rows > 0)
     hipLaunchKernelGGL(features_kernel, dim3((rows + 127) / 128), dim3(128), 0, st, G, chans, nch, mass7, X);
+  return hipGetLastError();
+}
+
+hipError_t launch_mlp_table(const float* X, int rows, const __bf16* pb, const float* P, float alpha, uint32_t* thr,
+                            float* mu, float* sigma, hipStream_t st) {
+  if (rows <= 0) return hipSuccess;
+  const int n_blocks = (rows + 15) / 16;
+  int grid = (n_blocks + kInfWaves - 1) / kInfWaves;
+  grid = grid > 512 ? 512 : grid;
+  hipLaunchKernelGGL(mlp_table_kernel, dim3(grid), dim3(kInfWaves * 64), 0, st, X, rows, pb, P, alpha, thr, mu, sigma);
   return hipGetLastError();
 }
 

@@ -156,17 +156,10 @@ qgbe_status qgbe::ensure_proposal_features(qgbe_ctx* c) {
 // context's stream.  Needs the weights, the table buffers (K = kMixK) and the
 // feature buffers in place.
 qgbe_status qgbe::refresh_proposal_table(qgbe_ctx* c) {
-  MlpState& m = c->mlp;
   const int rows = c->nch * c->G.nodes;
   HIP_TRY(launch_features(c->G, c->d_chans, c->nch, c->d_mass2, c->d_mass7, c->d_feat, c->stream), "features");
-  for (int r0 = 0; r0 < rows; r0 += kBatch) {
-    const int nr = std::min(kBatch, rows - r0);
-    HIP_TRY(launch_f32_to_bf16(c->d_feat + (size_t)r0 * kMlpIn, m.Xb, (size_t)nr * kMlpIn, c->stream), "features to bf16");
-    qgbe_status s = forward_staged(c, nr);
-    if (s) return s;
-    HIP_TRY(launch_table(m.Y, nr, c->table_alpha, c->d_thr + (size_t)r0 * kMixK, c->d_mu + (size_t)r0 * kMixK * 5,
-                         c->d_sigma + (size_t)r0 * kMixK * 5, c->stream), "proposal table");
-  }
+  HIP_TRY(launch_mlp_table(c->d_feat, rows, c->mlp.pb, c->mlp.params, c->table_alpha, c->d_thr, c->d_mu, c->d_sigma,
+                           c->stream), "proposal table");
   return QGBE_OK;
 }
 

@@ -45,6 +45,37 @@ LDS_PEAK = 256 * 32 * 2.4e9
 LDS_PER_ACCEPTED = 24 + 24     # 3 x 8 gathers, 3 x 8 atomic adds
 
 
+# HBM traffic of the collision kernel from rocprofv3 counters, valid only for
+# the kernel sources it was measured on (see kernel_sources_digest).
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "collide_f32_gg_16x16x1_20cube_pmc.md")
+KERNEL_SOURCES = ("collide.hip", "collide.h", "qgbe_common.h", "api.hip")
+
+
+def kernel_sources_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1912_04457_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch from the committed counter summary, or None when
+    the summary is for another workload or for other kernel sources."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith(("sources_sha256:", "workload:",
+                                                                                          "hbm_bytes_per_launch:")))
+    if fields.get("workload", "").strip() != workload:
+        return None
+    if fields.get("sources_sha256", "").strip() != kernel_sources_digest():
+        return None
+    return float(fields["hbm_bytes_per_launch"])
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -230,7 +261,8 @@ def main():
     slots = SLOTS_ACCEPTED * accepted + SLOTS_REJECTED * (evals - accepted)
     achieved = slots / t_coll.sum()
     roof = dict(bound="alu", achieved=achieved, peak=ALU_PEAK_SLOTS, unit="lane-op slots/s",
-                frac=achieved / ALU_PEAK_SLOTS, traffic=None,
+                frac=achieved / ALU_PEAK_SLOTS,
+                traffic=measured_traffic(wl.name) if a.samples in (0, wl.n_samples) else None,
                 kernel="collide_f32_kernel" if prec == qgbe.FP32 else "collide_f64_kernel",
                 kernel_ms_avg=float(t_coll.mean() * 1e3),
                 lds_frac=(LDS_PER_ACCEPTED * accepted / t_coll.sum()) / LDS_PEAK)

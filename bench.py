@@ -90,6 +90,7 @@ def parse():
     ap.add_argument("--no-fixed-error", action="store_true",
                     help="skip the plain-vs-learned time per step at fixed MC error")
     ap.add_argument("--replicas", type=int, default=8)
+    ap.add_argument("--train-epochs", type=int, default=4)
     return ap.parse_args()
 
 
@@ -101,7 +102,7 @@ def mc_error(reps):
     return float(np.sqrt(var.mean()) / np.sqrt((mean ** 2).mean()))
 
 
-def fixed_error(R):
+def fixed_error(R, epochs):
     """Time per step of the 7-species homogeneous workload (20^3 nodes, 70
     channels) with the plain symmetric sampler at 4096 samples per point,
     against the learned proposal at the smallest sample count whose MC error
@@ -147,7 +148,6 @@ def fixed_error(R):
         t0 = time.perf_counter()
         n_rows = qgbe.qgbe_record_samples(solver.ctx, per_item, 1, rows)
         qgbe.qgbe_proposal_set_weights(solver.ctx, W.random_mlp_params(1))
-        epochs = 6
         cfg = qgbe.TrainCfg(epochs=epochs, batch=4096, lr=2e-3, lr_final=1e-4, alpha=0.1, seed=1)
         losses = np.zeros(epochs)
         qgbe.qgbe_train_proposal(solver.ctx, rows, cfg, losses)
@@ -283,7 +283,7 @@ def main():
         "N_total_rel_drift": abs(stats[-1]["N_total"] - N0) / N0,
     }
     if not a.no_fixed_error:
-        out["fixed_mc_error"] = fixed_error(a.replicas)
+        out["fixed_mc_error"] = fixed_error(a.replicas, a.train_epochs)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, f0, N, a.cpu_seconds)
     print(json.dumps(out))

@@ -94,7 +94,7 @@ def lib():
         _lib.ref_collision_learned.argtypes = [p, p, p, u64, u32, i32, i32, p, p, p, i32, p,
                                                p, p, p, i32]
         _lib.ref_item_sums.restype = i32
-        _lib.ref_item_sums.argtypes = [p, p, p, u64, u32, i32, i32, C.c_int64, p, p, i32]
+        _lib.ref_item_sums.argtypes = [p, p, p, u64, u32, i32, i32, C.c_int64, p, p, p, i32]
         _lib.ref_collision_points.restype = i32
         _lib.ref_collision_points.argtypes = [p, p, p, C.c_int64, p, p, i32, i32, p, i32]
         _lib.ref_drift.restype = i32
@@ -282,17 +282,19 @@ def collision_learned(grid: Grid, f, mass2, seed: int, step: int, n_samples: int
 
 
 def item_sums(grid: Grid, f, mass2, seed: int, step: int, n_samples: int, items, *,
-              symmetric: bool = True, threads: int = 0) -> np.ndarray:
-    """Sum of the sample values of each selected (cell, channel, node) item."""
+              symmetric: bool = True, want_scale: bool = False, threads: int = 0):
+    """Sum of the sample values of each selected (cell, channel, node) item;
+    with want_scale also the sum of the samples' gain+loss magnitudes."""
     f = _field(grid, f)
     mass2 = _mass(grid, mass2)
     items = np.ascontiguousarray(items, dtype=np.int64).reshape(-1, 3)
     out = np.zeros(len(items))
+    scale = np.zeros(len(items)) if want_scale else None
     g = grid.c()
     if lib().ref_item_sums(C.byref(g), _ptr(f), _ptr(mass2), seed, step, n_samples, int(symmetric),
-                           len(items), _ptr(items), _ptr(out), threads) < 0:
+                           len(items), _ptr(items), _ptr(out), _ptr(scale), threads) < 0:
         raise ValueError("oracle rejected the arguments")
-    return out
+    return (out, scale) if want_scale else out
 
 
 def collision_points(grid: Grid, f, mass2, pts, wts, *, symmetric: bool = True,

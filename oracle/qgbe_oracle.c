@@ -515,11 +515,11 @@ static void run_item_uniform(const ref_grid* g, const ref_channel* ch, const dou
                              const double* mass2, uint64_t seed, uint32_t step, int32_t N,
                              int estimator, int symmetric, int flags,
                              const ref_equilibrium* eq, int64_t cell, int64_t p1_lin,
-                             accum* acc, double* item) {
+                             accum* acc, double* item, double* item_scale) {
   double p1[3];
   node_momentum(g, p1_lin, p1);
   const double Vp = box_volume(g);
-  double sum = 0.0;
+  double sum = 0.0, ssum = 0.0;
   for (int32_t s = 0; s < N; ++s) {
     uint32_t x[4];
     const uint32_t blk = (estimator == REF_EST_CM) ? 0u : 2u;
@@ -540,6 +540,7 @@ static void run_item_uniform(const ref_grid* g, const ref_channel* ch, const dou
       const double vd = ch->sigma * V5 * pt.g / N, vsd = ch->sigma * V5 * pt.gscale / N;
       deposit_sample(g, ch, acc, cell, p1_lin, (const double(*)[4])pt.k, symmetric, v, vs, vd, vsd);
       sum += symmetric ? v : vd;
+      ssum += symmetric ? vs : vsd;
     } else {
       const double V5 = Vp * (2.0 * g->p_half[0]) * (2.0 * g->p_half[1]);
       const double p3x = -g->p_half[0] + 2.0 * g->p_half[0] * u[3];
@@ -551,10 +552,12 @@ static void run_item_uniform(const ref_grid* g, const ref_channel* ch, const dou
         const double vd = ch->sigma * V5 * pts[r].g / N, vsd = ch->sigma * V5 * pts[r].gscale / N;
         deposit_sample(g, ch, acc, cell, p1_lin, (const double(*)[4])pts[r].k, symmetric, v, vs, vd, vsd);
         sum += symmetric ? v : vd;
+        ssum += symmetric ? vs : vsd;
       }
     }
   }
   if (item) *item = sum;
+  if (item_scale) *item_scale = ssum;
 }
 
 /* log of the mixture-of-logistic-normals density on the unit cube at the
@@ -694,7 +697,7 @@ static int32_t run_all(const run_args* ra, item_kind kind, double* A_out, double
     double* item = item_sum ? &item_sum[(cell * nch + ci) * nn + p1] : NULL;
     if (kind == ITEM_UNIFORM || (ra->chan_learned && !ra->chan_learned[ci])) {
       run_item_uniform(g, &chans[ci], ra->f, ra->mass2, ra->seed, ra->step, ra->N, ra->estimator,
-                       ra->symmetric, ra->flags, ra->eq, cell, p1, &acc, item);
+                       ra->symmetric, ra->flags, ra->eq, cell, p1, &acc, item, NULL);
     } else {
       const int64_t row = ((ra->table_per_cell ? cell : 0) * nch + ci) * nn + p1;
       run_item_learned(g, &chans[ci], ra->f, ra->mass2, ra->seed, ra->step, ra->N, ra->K,
@@ -717,7 +720,7 @@ static int32_t run_all(const run_args* ra, item_kind kind, double* A_out, double
    deposits; items[3*i .. 3*i+2] */
 int32_t ref_item_sums(const ref_grid* g, const double* f, const double* mass2, uint64_t seed,
                       uint32_t step, int32_t n_samples, int32_t symmetric, int64_t n_sel,
-                      const int64_t* items, double* out, int32_t n_threads) {
+                      const int64_t* items, double* out, double* out_scale, int32_t n_threads) {
   if (check_grid(g) || n_samples <= 0) return -1;
   ref_channel chans[128];
   const int nch = ref_channels(g, chans, 128);
@@ -739,7 +742,8 @@ int32_t ref_item_sums(const ref_grid* g, const double* f, const double* mass2, u
   for (int64_t i = 0; i < n_sel; ++i) {
     accum acc = {NULL, NULL};
     run_item_uniform(g, &chans[items[3 * i + 1]], f, mass2, seed, step, n_samples, REF_EST_CM,
-                     symmetric, 0, NULL, items[3 * i], items[3 * i + 2], &acc, &out[i]);
+                     symmetric, 0, NULL, items[3 * i], items[3 * i + 2], &acc, &out[i],
+                     out_scale ? &out_scale[i] : NULL);
   }
   return nch;
 }

@@ -111,10 +111,12 @@ int32_t ref_collision(const ref_grid* g, const double* f, const double* mass2,
                       double* item_sum, int32_t n_threads);
 
 /* direct sums (sum of sample values) of selected work items without any
-   deposits: items[3i..3i+2] = (cell, channel ordinal, node); out[n_sel] */
+   deposits: items[3i..3i+2] = (cell, channel ordinal, node); out[n_sel];
+   out_scale[n_sel] (may be NULL) receives the sum of the samples' gain+loss
+   magnitudes, the natural scale of each direct sum */
 int32_t ref_item_sums(const ref_grid* g, const double* f, const double* mass2, uint64_t seed,
                       uint32_t step, int32_t n_samples, int32_t symmetric, int64_t n_sel,
-                      const int64_t* items, double* out, int32_t n_threads);
+                      const int64_t* items, double* out, double* out_scale, int32_t n_threads);
 
 /* the collision term with a mixture-of-logistic-normals proposal.
  *   K          mixture components

@@ -219,3 +219,19 @@ def test_channel_fallback_routes_to_the_uniform_sampler(O):
         ref = it_l if flags[ci] else it_u
         assert np.array_equal(it_m[:, ci], ref[:, ci]), ci
     assert not np.array_equal(it_l, it_u)
+
+
+def test_item_scale_bounds_the_item_sum(O):
+    """The per-item scale (sum of the samples' gain+loss magnitudes) bounds the
+    item's direct sum and equals it where the loss term vanishes and |M|^2 > 0
+    (empty observed node f1 = 0, pure gluon)."""
+    g = O.Grid(n_p=(6, 6, 6), p_half=(2.0, 2.0, 2.0), species_mask=1 << G)
+    f = W.smooth_f(1, g.n_p, g.p_half, species_mask=g.species_mask)
+    empty = 37
+    f[G, 0, empty] = 0.0
+    m = O.masses(g, f)
+    items = np.array([[0, 0, n] for n in range(g.nodes)])
+    s, sc = O.item_sums(g, f, m, SEED, 1, 200, items, want_scale=True)
+    assert np.all(sc >= np.abs(s) * (1 - 1e-14))
+    assert sc[empty] > 0 and abs(s[empty] - sc[empty]) <= 1e-13 * sc[empty]
+    assert np.array_equal(s, O.item_sums(g, f, m, SEED, 1, 200, items))

@@ -1,0 +1,77 @@
+"""Parity at the benchmark sizes, in the launch configuration bench.py times.
+
+The oracle cannot evaluate a whole collision term of these workloads in a
+test's time, so it recomputes a seeded sample of work items one by one (their
+direct sums and scales), and properties that hold at any size are checked on
+the whole output: per-cell number conservation against the GPU's own scale,
+and particle-number conservation over steps.
+"""
+import numpy as np
+import pytest
+
+from paper_1912_04457_amd import qgbe
+from paper_1912_04457_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SEED = W.PHILOX_SEED
+
+
+def _case(name):
+    print(f"\n[gpu case] {name}", flush=True)
+
+
+def _solver(wl, **kw):
+    return qgbe.Solver(n_x=wl.n_x, n_p=wl.n_p, x_half=wl.x_half, p_half=wl.p_half,
+                       species_mask=wl.species_mask, alpha_s=wl.alpha_s, seed=SEED,
+                       precision=qgbe.FP32, **kw)
+
+
+def _sample_items(rng, cells, n_channels, nodes, k):
+    return np.stack([rng.integers(0, cells, k), rng.integers(0, n_channels, k), rng.integers(0, nodes, k)], 1)
+
+
+@pytest.mark.parametrize("wl", [W.C2, W.C3], ids=lambda w: w.name)
+def test_full_size_items_and_conservation(O, wl):
+    _case(f"full size {wl.name} N={wl.n_samples}")
+    f = W.initial_f(wl)
+    with _solver(wl) as s:
+        s.set_f(f)
+        qgbe.qgbe_set_step_index(s.ctx, 5)
+        A, S, I, st = s.collision(wl.n_samples, scale=True, items=True)
+        # the variant bench.py runs (no scale output): same samples, same item sums
+        A2, _, I2, _ = s.collision(wl.n_samples, items=True)
+        m = s.masses()
+        nch = s.n_channels
+    assert np.array_equal(I, I2)
+    assert np.all(np.abs(A - A2) <= 1e-12 * S + 1e-300)
+    # conservation per cell, at full size
+    for cell in range(wl.cells):
+        assert abs(A[:, cell].sum()) <= 1e-13 * S[:, cell].sum(), cell
+    # a seeded sample of items recomputed by the oracle
+    g = O.Grid(n_x=wl.n_x, n_p=wl.n_p, x_half=wl.x_half, p_half=wl.p_half,
+               species_mask=wl.species_mask, alpha_s=wl.alpha_s)
+    m_ref = O.masses(g, f)
+    assert np.allclose(m, m_ref, rtol=1e-13, atol=0)
+    rng = np.random.default_rng(77)
+    # half uniform over all items, half on nodes inside the occupied gluon sphere |p| < 1 GeV
+    inner = np.flatnonzero(np.linalg.norm(W.node_momenta(wl.n_p, wl.p_half), axis=1) < 1.0)
+    items = _sample_items(rng, wl.cells, nch, wl.nodes, 256)
+    items[128:, 2] = rng.choice(inner, 128)
+    ref, scale = O.item_sums(g, f, m_ref, SEED, 5, wl.n_samples, items, want_scale=True)
+    got = I[items[:, 0], items[:, 1], items[:, 2]]
+    err = np.abs(got - ref)
+    assert np.all(err <= 1e-4 * scale + 1e-300), float((err / np.maximum(scale, 1e-300)).max())
+    assert np.count_nonzero(scale) > 100
+
+
+def test_full_size_steps_conserve_number():
+    """Three steps of the pure-gluon spatial workload as bench.py runs it."""
+    _case("full size C2 steps")
+    wl = W.C2
+    with _solver(wl, drift=qgbe.DRIFT_UPWIND) as s:
+        s.set_f(W.initial_f(wl))
+        stats = s.step(wl.dt_fm, wl.n_samples, n_steps=3)
+    N = np.array([st["N_total"] for st in stats])
+    assert np.abs(N - N[0]).max() <= 1e-12 * N[0]
+    assert all(st["flags"] & qgbe.FLAG_NONFINITE == 0 for st in stats)

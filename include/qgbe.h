@@ -102,6 +102,13 @@ typedef struct {
   uint32_t flags;          /* QGBE_FLAG_*                                      */
   uint32_t step;           /* step index the stats belong to                   */
   double n_accepted;       /* evaluations above threshold and inside the box  */
+  double mc_err_est;       /* relative MC error of the collision term's direct
+                              sums, estimated from the samples themselves:
+                              sqrt(V / (Q - V)) with V = sum_i Var S_i and
+                              Q = sum_i S_i^2 over the work items i, S_i the
+                              item's sum of N sample values, Var S_i =
+                              N/(N-1) (sum v^2 - S_i^2/N); infinite when
+                              Q <= V (the sums are noise)                     */
 } qgbe_stats;
 
 /* Optional outputs of the collision term (all may be NULL). */

@@ -61,6 +61,7 @@ CollideArgs base_args(qgbe_ctx* c, int n_samples, double* A, double* scale, doub
   a.scale = scale;
   a.items = items;
   a.n_accepted = c->d_count;
+  a.mc_acc = c->d_mc;
   a.mix_K = c->K;
   a.mix_thr = c->d_thr;
   a.mix_mu = c->d_mu;
@@ -150,6 +151,7 @@ void plan_groups(qgbe_ctx* c) {
 // Enqueue the collision kernels accumulating into A (zeroed by the caller).
 qgbe_status run_collide(qgbe_ctx* c, int n_samples, bool learned, double* A, double* scale, double* items) {
   HIP_TRY(launch_zero_u64(c->d_count, c->stream), "zero counter");
+  HIP_TRY(launch_fill(c->d_mc, 0.0, 2, c->stream), "zero error accumulators");
   if (c->nch == 0) return QGBE_OK;
   CollideArgs a = base_args(c, n_samples, A, scale, items);
   a.learned = learned ? 1 : 0;
@@ -227,6 +229,8 @@ qgbe_status read_stats(qgbe_ctx* c, qgbe_stats* st) {
   unsigned long long accepted = 0;
   HIP_TRY(hipMemcpyAsync(&accepted, c->d_count, sizeof accepted, hipMemcpyDeviceToHost, c->stream),
           "copy counter");
+  double mc[2] = {0.0, 0.0};
+  HIP_TRY(hipMemcpyAsync(mc, c->d_mc, sizeof mc, hipMemcpyDeviceToHost, c->stream), "copy error accumulators");
   std::vector<double> m2((size_t)kSpecies * c->G.cells);
   HIP_TRY(hipMemcpyAsync(obs, c->d_obs, sizeof obs, hipMemcpyDeviceToHost, c->stream), "copy observables");
   HIP_TRY(hipMemcpyAsync(m2.data(), c->d_mass2, m2.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream),
@@ -234,6 +238,9 @@ qgbe_status read_stats(qgbe_ctx* c, qgbe_stats* st) {
   HIP_TRY(hipStreamSynchronize(c->stream), "synchronise");
   fill_stats(c, obs, m2.data(), st);
   st->n_accepted = (double)accepted;
+  // sum S_i^2 estimates sum (E S_i)^2 + sum Var S_i; remove the variance part
+  const double signal = mc[1] - mc[0];
+  st->mc_err_est = mc[0] <= 0.0 ? 0.0 : (signal > 0.0 ? std::sqrt(mc[0] / signal) : INFINITY);
   return QGBE_OK;
 }
 
@@ -318,6 +325,7 @@ qgbe_status qgbe_init_grid(const qgbe_grid_desc* desc, qgbe_ctx** out) {
   ALLOC(c->d_obs_scratch, observables_scratch(c->G), "observables scratch");
   ALLOC(c->d_obs, (size_t)observables_len, "observables");
   ALLOC(c->d_count, 1, "accepted counter");
+  ALLOC(c->d_mc, 2, "error accumulators");
 #undef ALLOC
   const char* what = "copy channel table";
   hipError_t e = hipSuccess;
@@ -370,6 +378,7 @@ void qgbe_destroy(qgbe_ctx* c) {
   (void)hipFree(c->d_obs_scratch);
   (void)hipFree(c->d_obs);
   (void)hipFree(c->d_count);
+  (void)hipFree(c->d_mc);
   (void)hipFree(c->d_thr);
   (void)hipFree(c->d_mu);
   (void)hipFree(c->d_sigma);

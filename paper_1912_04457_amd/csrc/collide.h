@@ -29,6 +29,8 @@ struct CollideArgs {
   double* scale;          // optional, same shape
   double* items;          // optional [cells][n_channels][nodes]
   unsigned long long* n_accepted;  // samples above threshold and inside the box
+  double* mc_acc;         // [2] (may be NULL): sum over items of the variance estimate of their
+                          // direct sum, and of the squared direct sums
   int learned;            // draw from the mixture table instead of uniformly
   int mix_K;              // mixture components
   const uint32_t* mix_thr;   // [channels*nodes][K]

@@ -521,6 +521,13 @@ __device__ __forceinline__ R weight_no_bracket(const Item& it, const Geo& g, int
 
 __device__ __forceinline__ bool is_gluon(int sp) { return sp == kGluon; }
 
+// Unbiased estimate of the variance of an item's direct sum S = sum_s v_s
+// over N samples: N/(N-1) (sum v^2 - S^2/N).
+__device__ __forceinline__ double item_variance(double s, double sq, int n) {
+  if (n < 2) return 0.0;
+  return fmax(0.0, (sq - s * s / n) * ((double)n / (n - 1)));
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -557,7 +564,7 @@ __global__ __launch_bounds__(256) void collide_f64_kernel(CollideArgs A) {
     const bool g1 = is_gluon(ch.sp[0]), g2 = is_gluon(ch.sp[1]);
     const bool g3 = is_gluon(ch.sp[2]), g4 = is_gluon(ch.sp[3]);
     const double F1 = g1 ? 1.0 + it.f1 : 1.0 - it.f1;
-    double dsum = 0.0, ssum = 0.0;
+    double dsum = 0.0, ssum = 0.0, dsq = 0.0;
     int n_ok = 0;
     const size_t mrow = (size_t)ci * G.nodes + p1_lin;
     const bool mix = kLearned && (!A.mix_on || A.mix_on[ci]);
@@ -595,6 +602,7 @@ __global__ __launch_bounds__(256) void collide_f64_kernel(CollideArgs A) {
       const double gain = f3 * f4 * F1 * F2, loss = it.f1 * f2 * F3 * F4;
       const double v = wnb * (gain - loss);
       dsum += v;
+      dsq = fma(v, v, dsq);
       const double vs = fabs(wnb) * (gain + loss);
       ssum += vs;
       if (A.symmetric) {
@@ -610,9 +618,14 @@ __global__ __launch_bounds__(256) void collide_f64_kernel(CollideArgs A) {
     }
     dsum = wave_sum(dsum);
     if (A.scale) ssum = wave_sum(ssum);
+    if (A.mc_acc) dsq = wave_sum(dsq);
     const int ok_total = wave_count(n_ok);
     if (lane == 0) {
       if (A.n_accepted) atomicAdd(A.n_accepted, (unsigned long long)ok_total);
+      if (A.mc_acc) {
+        atomicAdd(&A.mc_acc[0], item_variance(dsum, dsq, A.n_samples));
+        atomicAdd(&A.mc_acc[1], dsum * dsum);
+      }
       atomicAdd(Ac[0] + p1_lin, dsum);
       if (A.scale) atomicAdd(Sc[0] + p1_lin, ssum);
       if (A.items) A.items[((size_t)cell * A.n_channels + ci) * G.nodes + p1_lin] = dsum;
@@ -677,6 +690,7 @@ template <bool kSym, bool kScale, bool kTilesLds, bool kLearned>
 __global__ __launch_bounds__(f32_threads(kLearned)) void collide_f32_kernel(CollideArgs A) {
   extern __shared__ double lds[];
   __shared__ float mix_rows[kLearned ? f32_threads(true) / kWave : 1][kLearned ? kMixRow : 1];
+  __shared__ double mc_wg[2];  // this workgroup's item variances and squared item sums
   const Grid& G = A.G;
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
@@ -698,6 +712,7 @@ __global__ __launch_bounds__(f32_threads(kLearned)) void collide_f32_kernel(Coll
     goff[k] = ((size_t)sp * G.cells + cell) * nodes;
   }
   for (int i = threadIdx.x; i < n_acc * nodes; i += blockDim.x) acc[i] = 0.0;
+  if (threadIdx.x < 2) mc_wg[threadIdx.x] = 0.0;
   for (int k = 0; k < n_tiles; ++k)
     for (int i = threadIdx.x; i < nodes; i += blockDim.x) tiles[k * nodes + i] = A.f32[goff[k] + i];
   __syncthreads();
@@ -717,7 +732,7 @@ __global__ __launch_bounds__(f32_threads(kLearned)) void collide_f32_kernel(Coll
     }
     const float f1 = (float)it.f1;
     const float F1 = g1 ? 1.0f + f1 : 1.0f - f1;
-    double dsum = 0.0, ssum = 0.0;
+    double dsum = 0.0, ssum = 0.0, dsq = 0.0;
     int n_ok = 0;
     const size_t mrow = (size_t)ci * nodes + p1_lin;
     const bool mix = kLearned && (!A.mix_on || A.mix_on[ci]);
@@ -747,6 +762,7 @@ __global__ __launch_bounds__(f32_threads(kLearned)) void collide_f32_kernel(Coll
       const float gain = f3 * f4 * F1 * F2, loss = f1 * f2 * F3 * F4;
       const float v = wnb * (gain - loss);
       dsum += (double)v;
+      dsq = fma((double)v, (double)v, dsq);
       if (kScale) ssum += (double)(fabsf(wnb) * (gain + loss));
       if (kSym) {
         deposit_slot(k2, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off2, s2, v, nodes, G.ox, G.oy);
@@ -780,16 +796,21 @@ __global__ __launch_bounds__(f32_threads(kLearned)) void collide_f32_kernel(Coll
     if (!A.direct) continue;
     dsum = wave_sum(dsum);
     if (kScale) ssum = wave_sum(ssum);
+    dsq = wave_sum(dsq);
     const int ok_total = wave_count(n_ok);
     if (lane == 0) {
       if (A.n_accepted) atomicAdd(A.n_accepted, (unsigned long long)ok_total);
+      __hip_atomic_fetch_add(&mc_wg[0], item_variance(dsum, dsq, A.n_samples), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_WORKGROUP);
+      __hip_atomic_fetch_add(&mc_wg[1], dsum * dsum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       atomicAdd(A.A + ((size_t)ch.sp[0] * G.cells + cell) * nodes + p1_lin, dsum);
       if (kScale) atomicAdd(A.scale + ((size_t)ch.sp[0] * G.cells + cell) * nodes + p1_lin, ssum);
       if (A.items) A.items[((size_t)cell * A.n_channels + ci) * nodes + p1_lin] = dsum;
     }
   }
+  __syncthreads();
+  if (threadIdx.x < 2 && A.mc_acc && A.direct) atomicAdd(&A.mc_acc[threadIdx.x], mc_wg[threadIdx.x]);
   if (n_acc > 0) {
-    __syncthreads();
     for (int i = threadIdx.x; i < n_acc * nodes; i += blockDim.x) {
       const double v = acc[i];
       if (v != 0.0) {

@@ -46,13 +46,12 @@ hipError_t launch_nll(const float* Y, const float* yw, int yws, int rows, const 
                       double* loss, hipStream_t st);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, __bf16* pb, int n, float lr, float b1, float b2,
                        float eps, int t, hipStream_t st);
-hipError_t launch_table(const float* Y, int rows, float alpha, uint32_t* thr, float* mu, float* sigma, hipStream_t st);
 // Conditioning features of every (channel, node) row from the cell-averaged
 // masses; mass7 receives those 7 averages.
 hipError_t launch_features(const Grid& G, const Channel* chans, int nch, const double* mass2, double* mass7, float* X,
                            hipStream_t st);
 // Network forward on X [rows][8] straight into the proposal table (thr, mu,
-// sigma as launch_table writes them), activations kept on chip.
+// sigma in the layout of qgbe_set_proposal_table), activations kept on chip.
 hipError_t launch_mlp_table(const float* X, int rows, const __bf16* pb, const float* P, float alpha, uint32_t* thr,
                             float* mu, float* sigma, hipStream_t st);
 hipError_t launch_gather(const float* rows, const int* idx, int n, float* X, __bf16* Xb, float* yw, hipStream_t st);

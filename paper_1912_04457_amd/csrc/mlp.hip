@@ -183,31 +183,6 @@ __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g, 
   pb[i] = (__bf16)w;
 }
 
-// Proposal table from head rows (same format as qgbe_set_proposal_table).
-__global__ void table_kernel(const float* __restrict__ Y, int rows, float alpha, uint32_t* __restrict__ thr,
-                             float* __restrict__ mu, float* __restrict__ sigma) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= rows) return;
-  const float* h = Y + (size_t)r * kMlpOut;
-  double mx = -1e300;
-  for (int k = 0; k < kMixK; ++k) mx = fmax(mx, (double)h[k]);
-  double e[kMixK], se = 0.0;
-  for (int k = 0; k < kMixK; ++k) { e[k] = exp((double)h[k] - mx); se += e[k]; }
-  double cum = 0.0;
-  for (int k = 0; k < kMixK; ++k) {
-    const double lo = (double)alpha + (1.0 - (double)alpha) * cum;
-    double t = floor(lo * 4294967296.0);
-    t = t > 4294967295.0 ? 4294967295.0 : t;
-    thr[(size_t)r * kMixK + k] = (uint32_t)t;
-    cum += e[k] / se;
-    for (int d = 0; d < kMixD; ++d) {
-      mu[((size_t)r * kMixK + k) * kMixD + d] = h[kMixK + k * kMixD + d];
-      const float lr = h[kMixK + kMixK * kMixD + k * kMixD + d];
-      sigma[((size_t)r * kMixK + k) * kMixD + d] = expf(fminf(fmaxf(lr, kLsMin), kLsMax));
-    }
-  }
-}
-
 // Inference straight to the proposal table: each wave takes 16-row blocks of
 // X through the network (layer 1 on the vector ALUs, K = 8; layers 2 and 3 on
 // the matrix cores with the block's weights staged in LDS, transposed so the
@@ -436,11 +411,6 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, __bf16* pb,
                        float eps, int t, hipStream_t st) {
   const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
   hipLaunchKernelGGL(adam_kernel, dim3((n + 255) / 256), dim3(256), 0, st, p, g, m, v, pb, n, lr, b1, b2, eps, c1, c2);
-  return hipGetLastError();
-}
-
-hipError_t launch_table(const float* Y, int rows, float alpha, uint32_t* thr, float* mu, float* sigma, hipStream_t st) {
-  hipLaunchKernelGGL(table_kernel, dim3((rows + 127) / 128), dim3(128), 0, st, Y, rows, alpha, thr, mu, sigma);
   return hipGetLastError();
 }
 

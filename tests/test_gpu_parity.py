@@ -209,3 +209,24 @@ def test_errors_reported():
             qgbe.qgbe_set_distribution(s.ctx, 9, np.zeros((2, 120)))
         with pytest.raises(qgbe.QgbeError):
             qgbe.qgbe_step(s.ctx, -1.0, 8, 0, 1)
+
+
+@pytest.mark.parametrize("precision", [qgbe.FP64, qgbe.FP32])
+def test_mc_error_estimate_matches_replicas(precision):
+    """stats.mc_err_est (from each item's own samples) against the spread of
+    the item sums over independent replicas (other step indices)."""
+    _case(f"mc error estimate precision={precision}")
+    wl = W.C3.scaled(n_p=(8, 8, 8))
+    R, N = 16, 256
+    with qgbe.Solver(**_grid_kw(wl), precision=precision, seed=SEED) as s:
+        s.set_f(W.initial_f(wl))
+        est, items = [], []
+        for r in range(R):
+            qgbe.qgbe_set_step_index(s.ctx, 100 + r)
+            _, _, I, st = s.collision(N, items=True)
+            est.append(st.mc_err_est)
+            items.append(I)
+    I = np.array(items)
+    emp = np.sqrt(I.var(0, ddof=1).sum() / (I.mean(0) ** 2).sum())
+    print(f"[mc error] estimate {np.mean(est):.4f} (spread {np.std(est):.4f}), replicas {emp:.4f}", flush=True)
+    assert 0.8 < np.mean(est) / emp < 1.25

@@ -387,8 +387,9 @@ __device__ __forceinline__ void mix_draw_row(const uint32_t x[8], const uint32_t
     for (int d = 0; d < 5; ++d) {
       const uint32_t v = x[1 + d] >> 9;
       u[d] = unif23(v);
-      const float uf = ((float)v + 0.5f) * (1.0f / 8388608.0f);  // = u[d] exactly
-      y[d] = __logf(uf) - __logf(1.0f - uf);
+      const float uf = ((float)v + 0.5f) * (1.0f / 8388608.0f);  // = u[d] exactly, >= 2^-24
+      // logit u = ln 2 (log2 u - log2 (1 - u)); v_log_f32 is log2 (no denormals here)
+      y[d] = 0.6931471805599453f * (__builtin_amdgcn_logf(uf) - __builtin_amdgcn_logf(1.0f - uf));
     }
     return;
   }
@@ -447,34 +448,32 @@ __device__ __forceinline__ void mix_prepare_f32(const uint32_t* thr, const float
                                                 float* row, int lane) {
   for (int i = lane; i < K * 5; i += kWave) {
     row[i] = mu[i];
-    row[40 + i] = 1.0f / sg[i];
+    row[40 + i] = (float)rcp64((double)sg[i]);
     row[kMixSigma + i] = sg[i];
   }
   if (lane < K) {
     const double hi = lane + 1 < K ? (double)thr[lane + 1] : kTwo32;
-    const double pk = (hi - (double)thr[lane]) / kTwo32;
-    double c = pk > 0.0 ? log(pk) - 5.0 * kHalfLog2Pi : -1e30;
-    for (int d = 0; d < 5; ++d) c -= log((double)sg[lane * 5 + d]);
+    const double pk = (hi - (double)thr[lane]) * (1.0 / kTwo32);
+    double c = pk > 0.0 ? log64(pk) - 5.0 * kHalfLog2Pi : -1e30;
+    for (int d = 0; d < 5; ++d) c -= log64((double)sg[lane * 5 + d]);
     row[80 + lane] = (float)c;
   }
   if (lane == 0) row[88] = (float)((double)thr[0] / kTwo32);
 }
 
 __device__ __forceinline__ float mix_density_f32(const float* row, int K, const float yf[5]) {
-  float lk[16];
-  float mx = -1e30f;
+  // l_k <= log pi_k - sum_d log sigma_kd - 5/2 log 2pi <= 35 (sigma >= e^-7), so the
+  // exponentials need no max shift; all of them underflowing leaves q = alpha
+  float acc = 0.f;
   for (int k = 0; k < K; ++k) {
     float l = row[80 + k];
     for (int d = 0; d < 5; ++d) {
       const float z = (yf[d] - row[k * 5 + d]) * row[40 + k * 5 + d];
       l = fmaf(-0.5f * z, z, l);
     }
-    lk[k] = l;
-    mx = fmaxf(mx, l);
+    acc += __expf(l);
   }
-  float acc = 0.f;
-  for (int k = 0; k < K; ++k) acc += __expf(lk[k] - mx);
-  float lq = mx + __logf(acc);
+  float lq = __logf(acc);
   // log(u (1 - u)) = -|y| - 2 log(1 + e^-|y|)
   for (int d = 0; d < 5; ++d) {
     const float a = fabsf(yf[d]);

@@ -681,9 +681,10 @@ __device__ __forceinline__ void deposit_slot(int k, int slot_lo, int slot_hi, in
   else deposit<double, double>(out + off, widen(st), (double)v, ox, oy);
 }
 
-// Workgroup size: 12 waves for the uniform sampler (3 per SIMD at the
-// kernel's register count), 8 for the learned one (more registers per lane).
-constexpr int f32_threads(bool learned) { return learned ? 512 : 768; }
+// Workgroup size: 12 waves, 3 per SIMD (the register budget is then 168
+// VGPRs; the learned variant spills a few to scratch and still runs faster
+// than with 8 waves).
+constexpr int f32_threads(bool learned) { return learned ? 768 : 768; }
 
 template <bool kSym, bool kScale, bool kTilesLds, bool kLearned>
 __global__ __launch_bounds__(f32_threads(kLearned)) void collide_f32_kernel(CollideArgs A) {

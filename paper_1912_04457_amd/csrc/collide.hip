@@ -33,28 +33,26 @@ constexpr int kWave = 64;
 
 __device__ __forceinline__ double unif23(uint32_t v) { return ((double)v + 0.5) * (1.0 / 8388608.0); }
 
-// FP64 1/x and 1/sqrt(x) for finite x > 0: the hardware estimate (about 23
-// correct bits) refined by two Newton steps, which reaches the last bit
-// without the scaling and special-case handling of a general division or
-// square root.
+// FP64 1/x and 1/sqrt(x) for finite x > 0: the hardware estimate (measured
+// relative error below 2^-24 on gfx950) refined by one third-order step,
+// which leaves ~2^-72 (below the last bit) without the scaling and
+// special-case handling of a general division or square root.
+//   1/x:       e = 1 - x r,          r (1 + e + e^2)
+//   1/sqrt(x): t = (1 - x y^2) / 2,  y (1 + t + 3/2 t^2)
 __device__ __forceinline__ double rcp64(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-x, r, 1.0);
-  return fma(r, e, r);
+  const double r = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, r, 1.0);
+  return fma(r, fma(e, e, e), r);
 }
 
 __device__ __forceinline__ double rsqrt64(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  const double h = 0.5 * x;
-  double t = fma(-h * y, y, 0.5);
-  y = fma(y, t, y);
-  t = fma(-h * y, y, 0.5);
-  return fma(y, t, y);
+  const double y = __builtin_amdgcn_rsq(x);
+  const double t = fma(-0.5 * x * y, y, 0.5);
+  return fma(y, fma(1.5 * t, t, t), y);
 }
 
-// sqrt for x >= 0 (0 maps to 0)
+__device__ __forceinline__ double sqrt64(double x) { return x > 0.0 ? x * rsqrt64(x) : 0.0; }
+
 // sin and cos of 2 pi u for u in [0, 1).  With x = 2u = q/2 + r, q the
 // nearest multiple of 1/2 (exact: u has at most 24 significant bits) and
 // |r| <= 1/4, the Taylor series of sin(pi r) to r^15 and of cos(pi r) to
@@ -141,7 +139,6 @@ __device__ __forceinline__ double log64(double a) {
   return fma(de, 0.6931471805598903, fma(de, 5.497923018708371e-14, 2.0 * s * p));
 }
 
-__device__ __forceinline__ double sqrt64(double x) { return x > 0.0 ? x * rsqrt64(x) : 0.0; }
 
 template <typename R>
 __device__ __forceinline__ R rcp_r(R x);
@@ -243,8 +240,8 @@ struct Item {
   double p1[3];
   double E1;
   double m2sq, m3sq, m4sq;
-  double thr;               // (m3 + m4)^2
-  double sum2, dif2;        // (m3 + m4)^2, (m3 - m4)^2
+  double dm34;              // m3^2 - m4^2
+  double sum2, dif2;        // (m3 + m4)^2 (the threshold of s), (m3 - m4)^2
   double mu;                // regulator m_g^2
   double f1;
   double coef;              // w V5 / N (symmetric) or sigma V5 / N (direct)
@@ -265,7 +262,7 @@ __device__ __forceinline__ bool geometry(const Item& it, const Grid& G, const do
   const double P[3] = {it.p1[0] + g.p2[0], it.p1[1] + g.p2[1], it.p1[2] + g.p2[2]};
   const double s = E * E - (P[0] * P[0] + P[1] * P[1] + P[2] * P[2]);
   g.s = s;
-  if (!(s > it.thr)) return false;
+  if (!(s > it.sum2)) return false;  // threshold (m3 + m4)^2
   const double rs = rsqrt64(s);
   const double sq = s * rs;
   g.rs = rs;
@@ -290,7 +287,7 @@ __device__ __forceinline__ bool geometry(const Item& it, const Grid& G, const do
   const double sc = sth * cphi, ss = sth * sphi;
   double p3s[3];
   for (int k = 0; k < 3; ++k) p3s[k] = g.pstar * (sc * e1[k] + ss * e2[k] + cth * n[k]);
-  const double E3s = 0.5 * (s + it.m3sq - it.m4sq) * rs;
+  const double E3s = 0.5 * (s + it.dm34) * rs;
   const double Pp3 = P[0] * p3s[0] + P[1] * p3s[1] + P[2] * p3s[2];
   const double c3 = (Pp3 * inv_E + E3s) * rs;
   for (int k = 0; k < 3; ++k) {
@@ -502,7 +499,7 @@ __device__ __forceinline__ void load_item(Item& it, const CollideArgs& A, const 
   const double m3 = sqrt(it.m3sq), m4 = sqrt(it.m4sq);
   it.sum2 = (m3 + m4) * (m3 + m4);
   it.dif2 = (m3 - m4) * (m3 - m4);
-  it.thr = it.sum2;
+  it.dm34 = it.m3sq - it.m4sq;
   it.f1 = A.f64[((size_t)ch.sp[0] * G.cells + cell) * G.nodes + p1_lin];
   const double V5 = G.Vp * 4.0 * kPi;
   it.coef = (A.symmetric ? ch.w : ch.sigma) * V5 / (double)A.n_samples;
@@ -656,13 +653,13 @@ __device__ __forceinline__ R interpolate_quads(const float4* __restrict__ q4, co
   return b0 + st.wx * (b1 - b0);
 }
 
-template <bool kTilesLds, typename R>
+template <bool kAllLds, typename R>
 __device__ __forceinline__ R interp_slot(int k, int n_tiles, const float* tiles, const float4* __restrict__ f32q,
                                          size_t off, const Stencil<R>& st, int nodes, int ox, int oy) {
   // an address-space-qualified view keeps the LDS reads ds_read instructions
   // instead of generic flat loads
   typedef __attribute__((address_space(3))) const float LdsF32;
-  if (kTilesLds || k < n_tiles) return interpolate<R>((LdsF32*)(tiles + k * nodes), st, ox, oy);
+  if (kAllLds || k < n_tiles) return interpolate<R>((LdsF32*)(tiles + k * nodes), st, ox, oy);
   return interpolate_quads<R>(f32q + off, st, ox);
 }
 
@@ -672,13 +669,16 @@ __device__ __forceinline__ Stencil<double> widen(const Stencil<float>& st) {
   return Stencil<double>{st.base, (double)st.wx, (double)st.wy, (double)st.wz};
 }
 
+template <bool kAllLds>
 __device__ __forceinline__ void deposit_slot(int k, int slot_lo, int slot_hi, int n_acc, double* acc,
                                              double* __restrict__ out, size_t off, const Stencil<float>& st,
                                              float v, int nodes, int ox, int oy) {
   if (k < slot_lo || k >= slot_hi) return;  // deposited by another launch
   const int j = k - slot_lo;
-  if (j < n_acc) deposit<double, double, __HIP_MEMORY_SCOPE_WORKGROUP>(acc + j * nodes, widen(st), (double)v, ox, oy);
-  else deposit<double, double>(out + off, widen(st), (double)v, ox, oy);
+  if (kAllLds || j < n_acc)
+    deposit<double, double, __HIP_MEMORY_SCOPE_WORKGROUP>(acc + j * nodes, widen(st), (double)v, ox, oy);
+  else
+    deposit<double, double>(out + off, widen(st), (double)v, ox, oy);
 }
 
 // Workgroup size: 12 waves, 3 per SIMD (the register budget is then 168
@@ -686,7 +686,7 @@ __device__ __forceinline__ void deposit_slot(int k, int slot_lo, int slot_hi, in
 // than with 8 waves).
 constexpr int f32_threads(bool learned) { return learned ? 768 : 768; }
 
-template <bool kSym, bool kScale, bool kTilesLds, bool kLearned>
+template <bool kSym, bool kScale, bool kAllLds, bool kLearned>
 __global__ __launch_bounds__(f32_threads(kLearned)) void collide_f32_kernel(CollideArgs A) {
   extern __shared__ double lds[];
   __shared__ float mix_rows[kLearned ? f32_threads(true) / kWave : 1][kLearned ? kMixRow : 1];
@@ -753,9 +753,9 @@ __global__ __launch_bounds__(f32_threads(kLearned)) void collide_f32_kernel(Coll
       const Stencil<float> s2 = make_stencil<float>(g.p2, G);
       const Stencil<float> s3 = make_stencil<float>(g.p3, G);
       const Stencil<float> s4 = make_stencil<float>(g.p4, G);
-      const float f2 = interp_slot<kTilesLds, float>(k2, n_tiles, tiles, A.f32q, off2, s2, nodes, G.ox, G.oy);
-      const float f3 = interp_slot<kTilesLds, float>(k3, n_tiles, tiles, A.f32q, off3, s3, nodes, G.ox, G.oy);
-      const float f4 = interp_slot<kTilesLds, float>(k4, n_tiles, tiles, A.f32q, off4, s4, nodes, G.ox, G.oy);
+      const float f2 = interp_slot<kAllLds, float>(k2, n_tiles, tiles, A.f32q, off2, s2, nodes, G.ox, G.oy);
+      const float f3 = interp_slot<kAllLds, float>(k3, n_tiles, tiles, A.f32q, off3, s3, nodes, G.ox, G.oy);
+      const float f4 = interp_slot<kAllLds, float>(k4, n_tiles, tiles, A.f32q, off4, s4, nodes, G.ox, G.oy);
       const float F2 = g2 ? 1.0f + f2 : 1.0f - f2;
       const float F3 = g3 ? 1.0f + f3 : 1.0f - f3;
       const float F4 = g4 ? 1.0f + f4 : 1.0f - f4;
@@ -765,9 +765,9 @@ __global__ __launch_bounds__(f32_threads(kLearned)) void collide_f32_kernel(Coll
       dsq = fma((double)v, (double)v, dsq);
       if (kScale) ssum += (double)(fabsf(wnb) * (gain + loss));
       if (kSym) {
-        deposit_slot(k2, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off2, s2, v, nodes, G.ox, G.oy);
-        deposit_slot(k3, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off3, s3, -v, nodes, G.ox, G.oy);
-        deposit_slot(k4, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off4, s4, -v, nodes, G.ox, G.oy);
+        deposit_slot<kAllLds>(k2, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off2, s2, v, nodes, G.ox, G.oy);
+        deposit_slot<kAllLds>(k3, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off3, s3, -v, nodes, G.ox, G.oy);
+        deposit_slot<kAllLds>(k4, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off4, s4, -v, nodes, G.ox, G.oy);
         if (kScale && A.direct) {
           const float vs = fabsf(wnb) * (gain + loss);
           deposit<double, double>(A.scale + ((size_t)ch.sp[1] * G.cells + cell) * nodes, widen(s2), (double)vs, G.ox, G.oy);
@@ -907,17 +907,17 @@ hipError_t launch_collide_f64(const CollideArgs& a, hipStream_t stream) {
 }
 
 template <bool kSym, bool kScale, bool kLearned>
-void launch_f32_variant(const CollideArgs& a, bool tiles_lds, dim3 grid, dim3 block, size_t lds, hipStream_t st) {
-  if (tiles_lds)
+void launch_f32_variant(const CollideArgs& a, bool all_lds, dim3 grid, dim3 block, size_t lds, hipStream_t st) {
+  if (all_lds)
     hipLaunchKernelGGL((collide_f32_kernel<kSym, kScale, true, kLearned>), grid, block, lds, st, a);
   else
     hipLaunchKernelGGL((collide_f32_kernel<kSym, kScale, false, kLearned>), grid, block, lds, st, a);
 }
 
 template <bool kSym, bool kScale>
-void launch_f32_sampler(const CollideArgs& a, bool tiles_lds, dim3 grid, dim3 block, size_t lds, hipStream_t st) {
-  if (a.learned) launch_f32_variant<kSym, kScale, true>(a, tiles_lds, grid, block, lds, st);
-  else launch_f32_variant<kSym, kScale, false>(a, tiles_lds, grid, block, lds, st);
+void launch_f32_sampler(const CollideArgs& a, bool all_lds, dim3 grid, dim3 block, size_t lds, hipStream_t st) {
+  if (a.learned) launch_f32_variant<kSym, kScale, true>(a, all_lds, grid, block, lds, st);
+  else launch_f32_variant<kSym, kScale, false>(a, all_lds, grid, block, lds, st);
 }
 
 int collide_f32_waves(bool learned) { return f32_threads(learned) / kWave; }
@@ -926,17 +926,19 @@ hipError_t launch_collide_f32(const CollideArgs& a, int nslot, hipStream_t strea
   const int threads = f32_threads(a.learned != 0);
   const int n_acc = a.symmetric ? std::min(a.slot_hi - a.slot_lo, a.lds_acc) : 0;
   const int n_tiles = std::min(nslot, a.lds_tiles);
-  const bool tiles_lds = n_tiles == nslot;
+  // every tile and every accumulator of this launch's slots in LDS: the
+  // variant without global-memory paths
+  const bool all_lds = n_tiles == nslot && (!a.symmetric || n_acc == a.slot_hi - a.slot_lo);
   const size_t lds = (size_t)n_acc * a.G.nodes * sizeof(double) + (size_t)n_tiles * a.G.nodes * sizeof(float);
   const long long blocks = (long long)a.G.cells * a.n_group * a.n_chunks;
   if (blocks <= 0) return hipSuccess;
   const dim3 grid((unsigned)blocks), block(threads);
   if (a.symmetric) {
-    if (a.scale) launch_f32_sampler<true, true>(a, tiles_lds, grid, block, lds, stream);
-    else launch_f32_sampler<true, false>(a, tiles_lds, grid, block, lds, stream);
+    if (a.scale) launch_f32_sampler<true, true>(a, all_lds, grid, block, lds, stream);
+    else launch_f32_sampler<true, false>(a, all_lds, grid, block, lds, stream);
   } else {
-    if (a.scale) launch_f32_sampler<false, true>(a, tiles_lds, grid, block, lds, stream);
-    else launch_f32_sampler<false, false>(a, tiles_lds, grid, block, lds, stream);
+    if (a.scale) launch_f32_sampler<false, true>(a, all_lds, grid, block, lds, stream);
+    else launch_f32_sampler<false, false>(a, all_lds, grid, block, lds, stream);
   }
   return hipGetLastError();
 }

@@ -182,7 +182,9 @@ qgbe_status qgbe_restore(qgbe_ctx* ctx, const void* buf, size_t bytes);
  * n_samples samples per (cell, channel, node); sampler QGBE_SAMPLER_UNIFORM
  * draws p2 uniformly in the momentum box and the two CM angles uniformly
  * (Eq. MC C_gg with the CM-angle parameterisation), QGBE_SAMPLER_LEARNED
- * draws from the proposal table (qgbe_set_proposal_table).
+ * draws from the proposal table (qgbe_set_proposal_table, or the network's
+ * table re-evaluated on the current masses after qgbe_proposal_build_table),
+ * with weight 1/q, except on channels set back to the uniform sampler.
  * Symmetric sampling (Eq. small c relation) adds each sample's value at the
  * observed node and at the trilinear stencils of the other three momenta with
  * signs (+,+,-,-), so sum_{Y,q} A = 0 per cell exactly.
@@ -200,8 +202,10 @@ qgbe_status qgbe_collision_term_ex(qgbe_ctx* ctx, int32_t n_samples, int32_t sam
  *   the central differences of Eq. descrete left hand, periodic) ->
  *   f += dt (A / (N_Y hbar c) - D[f]) -> observables.
  * dt_fm in fm/c, hbar c = 0.1973269804 GeV fm.  Non-evolving species are
- * frozen.  per_step: n_steps entries or NULL.  Returns QGBE_ENUMERIC (after
- * finishing the step) if f became non-finite. */
+ * frozen.  The sampler is as in qgbe_collision_term (a network-built table is
+ * re-evaluated at every step).  per_step: n_steps entries or NULL (their
+ * t_step_ms covers masses, table, collision term and update).  Returns
+ * QGBE_ENUMERIC (after finishing the step) if f became non-finite. */
 qgbe_status qgbe_step(qgbe_ctx* ctx, double dt_fm, int32_t n_samples, int32_t sampler,
                       int32_t n_steps, qgbe_stats* per_step);
 

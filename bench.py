@@ -43,6 +43,7 @@ ALU_PEAK_SLOTS = 256 * 64 * 2.4e9
 # LDS: 128 B/clk/CU -> 32 four-byte lane accesses per clock per CU
 LDS_PEAK = 256 * 32 * 2.4e9
 LDS_PER_ACCEPTED = 24 + 24     # 3 x 8 gathers, 3 x 8 atomic adds
+HBM_PEAK = 8.0e12               # bytes/s
 
 
 # HBM traffic of the collision kernel from rocprofv3 counters, valid only for
@@ -260,12 +261,14 @@ def main():
     value = evals / elapsed
     slots = SLOTS_ACCEPTED * accepted + SLOTS_REJECTED * (evals - accepted)
     achieved = slots / t_coll.sum()
+    traffic = measured_traffic(wl.name) if a.samples in (0, wl.n_samples) else None
     roof = dict(bound="alu", achieved=achieved, peak=ALU_PEAK_SLOTS, unit="lane-op slots/s",
                 frac=achieved / ALU_PEAK_SLOTS,
-                traffic=measured_traffic(wl.name) if a.samples in (0, wl.n_samples) else None,
+                traffic=traffic,
                 kernel="collide_f32_kernel" if prec == qgbe.FP32 else "collide_f64_kernel",
                 kernel_ms_avg=float(t_coll.mean() * 1e3),
-                lds_frac=(LDS_PER_ACCEPTED * accepted / t_coll.sum()) / LDS_PEAK)
+                lds_frac=(LDS_PER_ACCEPTED * accepted / t_coll.sum()) / LDS_PEAK,
+                hbm_frac=None if traffic is None else traffic / float(t_coll.mean()) / HBM_PEAK)
     N0 = stats[0]["N_total"]
     out = {
         "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": a.steps,

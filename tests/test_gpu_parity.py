@@ -106,6 +106,20 @@ def test_config3_lds_layout_fp32(O):
     assert abs(r["A"].sum()) <= 1e-13 * r["S_ref"].sum()
 
 
+@pytest.mark.parametrize("n_p,mask,N", [((32, 32, 32), 1 << 6, 4), ((24, 24, 24), 0x7F, 2)],
+                         ids=["g_32cube", "qg7_24cube"])
+def test_large_grid_lds_plans_fp32(O, n_p, mask, N):
+    """Grids whose FP64 accumulators do not fit in LDS (32^3: none, global
+    atomics; 24^3: one per launch) next to FP32 tiles in LDS or in the
+    global node quads."""
+    _case(f"large grid {n_p} mask={mask:#x} N={N}")
+    wl = W.C3.scaled(n_p=n_p, species_mask=mask)
+    f = W.initial_f(wl)
+    r = _run_pair(O, wl, f, N, qgbe.FP32)
+    _compare(r["A"], r["A_ref"], r["S_ref"], 1e-4, "A")
+    assert abs(r["A"].sum()) <= 1e-13 * r["S_ref"].sum()
+
+
 def test_spatial_small_fp32(O):
     """4x4x1 cells of a Gaussian transverse profile, 8^3 momenta, N = 96."""
     _case("spatial small fp32")

@@ -103,6 +103,31 @@ def mc_error(reps):
     return float(np.sqrt(var.mean()) / np.sqrt((mean ** 2).mean()))
 
 
+def train_proposal(solver, wl, epochs, target_rows=1_000_000):
+    """Record ~10^6 uniform samples of the workload itself (every k-th work
+    item), train the network on the GPU, run the fallback judge; the table
+    then follows the masses at every learned step."""
+    import torch
+    items = wl.cells * solver.n_channels * wl.nodes
+    per_item = max(1, -(-target_rows // items))
+    stride = max(1, items * per_item // target_rows)
+    n_sel = -(-items // stride)
+    rows = torch.empty((n_sel * per_item, qgbe.RECORD_WIDTH), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_rows = qgbe.qgbe_record_samples(solver.ctx, per_item, stride, rows)
+    qgbe.qgbe_proposal_set_weights(solver.ctx, W.random_mlp_params(1))
+    cfg = qgbe.TrainCfg(epochs=epochs, batch=4096, lr=2e-3, lr_final=1e-4, alpha=0.1, seed=1)
+    losses = np.zeros(epochs)
+    qgbe.qgbe_train_proposal(solver.ctx, rows, cfg, losses)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    del rows
+    flags, _ = qgbe.qgbe_proposal_judge(solver.ctx, 32, 1, solver.n_channels)
+    return dict(train_rows=n_rows, train_epochs=epochs, train_s=train_s, train_loss_last=float(losses[-1]),
+                learned_channels=int(flags.sum()), channels=solver.n_channels)
+
+
 def fixed_error(R, epochs):
     """Time per step of the 7-species homogeneous workload (20^3 nodes, 70
     channels) with the plain symmetric sampler at 4096 samples per point,
@@ -246,11 +271,16 @@ def main():
                          species_mask=wl.species_mask, alpha_s=wl.alpha_s, precision=prec,
                          drift=drift, seed=W.PHILOX_SEED, device=0)
     solver.set_f(f0)
+    sampler = qgbe.SAMPLER_UNIFORM
+    prep = None
+    if wl.sampler == "learned":
+        prep = train_proposal(solver, wl, a.train_epochs)
+        sampler = qgbe.SAMPLER_LEARNED
     if a.warmup:
-        solver.step(wl.dt_fm, N, n_steps=a.warmup)
+        solver.step(wl.dt_fm, N, n_steps=a.warmup, sampler=sampler)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    stats = solver.step(wl.dt_fm, N, n_steps=a.steps)
+    stats = solver.step(wl.dt_fm, N, n_steps=a.steps, sampler=sampler)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     solver.close()
@@ -277,14 +307,17 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "cells": wl.cells, "momentum_nodes": wl.nodes,
                    "species_mask": wl.species_mask, "channels": solver.n_channels,
-                   "samples_per_point": N, "sampler": "uniform", "symmetric": True,
+                   "samples_per_point": N, "sampler": wl.sampler, "symmetric": True,
                    "precision": "fp32 integrand, fp64 geometry + accumulation" if prec == qgbe.FP32
                    else "fp64", "drift": wl.drift, "dt_fm": wl.dt_fm},
         "roofline": roof,
         "accepted_fraction": accepted / evals,
         "collide_ms_per_step": float(t_coll.mean() * 1e3),
         "N_total_rel_drift": abs(stats[-1]["N_total"] - N0) / N0,
+        "mc_err_est": float(np.mean([s["mc_err_est"] for s in stats])),
     }
+    if prep is not None:
+        out["proposal"] = prep
     if not a.no_fixed_error:
         out["fixed_mc_error"] = fixed_error(a.replicas, a.train_epochs)
     if not a.no_cpu_baseline:

@@ -234,14 +234,14 @@ qgbe_status qgbe_set_channel_samplers(qgbe_ctx* ctx, const uint8_t* use_learned)
 qgbe_status qgbe_get_channel_samplers(qgbe_ctx* ctx, uint8_t* use_learned);
 
 /* The fallback judge of the learned proposal: n_reps pilot collision terms of
- * n_pilot samples per point with each sampler (on a key range of their own),
- * then per channel the summed variance of the per-(cell, node) estimates
- * times the sampler's pilot time; a channel keeps the learned sampler only if
- * that product is smaller than the uniform one.  Installs the decision and
+ * n_pilot samples per point with each sampler (on a key range of their own);
+ * per channel, the variance of every (cell, node) estimate is estimated from
+ * its own samples (as for mc_err_est), summed, and multiplied by the
+ * sampler's pilot time; a channel keeps the learned sampler only if that
+ * product is smaller than the uniform one.  Installs the decision and
  * returns it in use_learned[channels] (may be NULL); ratio[channels] (may be
  * NULL) receives learned / uniform variance x time.  The step index and f are
- * left as they were.  Allocates a pilot buffer of cells*channels*nodes
- * doubles for the call. */
+ * left as they were.  n_pilot >= 2, n_reps >= 1. */
 qgbe_status qgbe_proposal_judge(qgbe_ctx* ctx, int32_t n_pilot, int32_t n_reps, uint8_t* use_learned,
                                 double* ratio);
 

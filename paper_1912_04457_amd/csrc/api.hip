@@ -62,6 +62,7 @@ CollideArgs base_args(qgbe_ctx* c, int n_samples, double* A, double* scale, doub
   a.items = items;
   a.n_accepted = c->d_count;
   a.mc_acc = c->d_mc;
+  a.chan_var = c->d_chan_var;
   a.mix_K = c->K;
   a.mix_thr = c->d_thr;
   a.mix_mu = c->d_mu;
@@ -152,6 +153,7 @@ void plan_groups(qgbe_ctx* c) {
 qgbe_status run_collide(qgbe_ctx* c, int n_samples, bool learned, double* A, double* scale, double* items) {
   HIP_TRY(launch_zero_u64(c->d_count, c->stream), "zero counter");
   HIP_TRY(launch_fill(c->d_mc, 0.0, 2, c->stream), "zero error accumulators");
+  HIP_TRY(launch_fill(c->d_chan_var, 0.0, std::max(1, c->nch), c->stream), "zero channel variances");
   if (c->nch == 0) return QGBE_OK;
   CollideArgs a = base_args(c, n_samples, A, scale, items);
   a.learned = learned ? 1 : 0;
@@ -326,6 +328,7 @@ qgbe_status qgbe_init_grid(const qgbe_grid_desc* desc, qgbe_ctx** out) {
   ALLOC(c->d_obs, (size_t)observables_len, "observables");
   ALLOC(c->d_count, 1, "accepted counter");
   ALLOC(c->d_mc, 2, "error accumulators");
+  ALLOC(c->d_chan_var, std::max(1, c->nch), "channel variances");
 #undef ALLOC
   const char* what = "copy channel table";
   hipError_t e = hipSuccess;
@@ -379,6 +382,7 @@ void qgbe_destroy(qgbe_ctx* c) {
   (void)hipFree(c->d_obs);
   (void)hipFree(c->d_count);
   (void)hipFree(c->d_mc);
+  (void)hipFree(c->d_chan_var);
   (void)hipFree(c->d_thr);
   (void)hipFree(c->d_mu);
   (void)hipFree(c->d_sigma);

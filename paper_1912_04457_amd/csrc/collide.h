@@ -31,6 +31,7 @@ struct CollideArgs {
   unsigned long long* n_accepted;  // samples above threshold and inside the box
   double* mc_acc;         // [2] (may be NULL): sum over items of the variance estimate of their
                           // direct sum, and of the squared direct sums
+  double* chan_var;       // [channels] (may be NULL): the variance sum per channel
   int learned;            // draw from the mixture table instead of uniformly
   int mix_K;              // mixture components
   const uint32_t* mix_thr;   // [channels*nodes][K]

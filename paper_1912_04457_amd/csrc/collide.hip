@@ -619,8 +619,10 @@ __global__ __launch_bounds__(256) void collide_f64_kernel(CollideArgs A) {
     if (lane == 0) {
       if (A.n_accepted) atomicAdd(A.n_accepted, (unsigned long long)ok_total);
       if (A.mc_acc) {
-        atomicAdd(&A.mc_acc[0], item_variance(dsum, dsq, A.n_samples));
+        const double var = item_variance(dsum, dsq, A.n_samples);
+        atomicAdd(&A.mc_acc[0], var);
         atomicAdd(&A.mc_acc[1], dsum * dsum);
+        if (A.chan_var) atomicAdd(&A.chan_var[ci], var);
       }
       atomicAdd(Ac[0] + p1_lin, dsum);
       if (A.scale) atomicAdd(Sc[0] + p1_lin, ssum);
@@ -810,6 +812,7 @@ __global__ __launch_bounds__(f32_threads(kLearned)) void collide_f32_kernel(Coll
   }
   __syncthreads();
   if (threadIdx.x < 2 && A.mc_acc && A.direct) atomicAdd(&A.mc_acc[threadIdx.x], mc_wg[threadIdx.x]);
+  if (threadIdx.x == 0 && A.chan_var && A.direct) atomicAdd(&A.chan_var[ci], mc_wg[0]);  // one channel per workgroup
   if (n_acc > 0) {
     for (int i = threadIdx.x; i < n_acc * nodes; i += blockDim.x) {
       const double v = acc[i];

@@ -356,52 +356,34 @@ qgbe_status qgbe_get_channel_samplers(qgbe_ctx* c, uint8_t* use_learned) {
 qgbe_status qgbe_proposal_judge(qgbe_ctx* c, int32_t n_pilot, int32_t n_reps, uint8_t* use_learned,
                                 double* ratio) {
   if (!c) return fail(QGBE_EINVAL, "NULL context");
-  if (n_pilot < 1 || n_reps < 2) return fail(QGBE_EINVAL, "n_pilot >= 1 and n_reps >= 2 required");
+  if (n_pilot < 2 || n_reps < 1) return fail(QGBE_EINVAL, "n_pilot >= 2 and n_reps >= 1 required");
   if (!c->K) return fail(QGBE_ESTATE, "no proposal table installed");
   HIP_TRY(hipSetDevice(c->d.device), "hipSetDevice");
-  const size_t n_items = (size_t)c->G.cells * c->nch * c->G.nodes;
-  if (n_items == 0) return QGBE_OK;
-  double* d_items = nullptr;
-  HIP_TRY(hipMalloc(&d_items, n_items * sizeof(double)), "pilot scratch");
-  std::vector<double> h(n_items), sum[2], sq[2];
+  const int nch = std::max(1, c->nch);
+  std::vector<double> var[2], h(nch);
   double t_ms[2] = {0.0, 0.0};
   const uint32_t saved_step = c->step;
   qgbe_status s = reset_channel_samplers(c);
   for (int l = 0; l < 2 && !s; ++l) {
-    sum[l].assign(n_items, 0.0);
-    sq[l].assign(n_items, 0.0);
+    var[l].assign(nch, 0.0);
     for (int r = 0; r < n_reps && !s; ++r) {
       // pilot draws use their own key range, apart from the run's steps
       c->step = 0xF0000000u + (uint32_t)r;
-      qgbe_collide_extras ex{nullptr, d_items, 1};
       qgbe_stats st;
-      s = qgbe_collision_term_ex(c, n_pilot, l ? QGBE_SAMPLER_LEARNED : QGBE_SAMPLER_UNIFORM, c->d_A, 1, &ex, &st);
+      s = qgbe_collision_term_ex(c, n_pilot, l ? QGBE_SAMPLER_LEARNED : QGBE_SAMPLER_UNIFORM, c->d_A, 1, nullptr, &st);
       if (s) break;
       t_ms[l] += st.t_collide_ms;
-      hipError_t e = hipMemcpy(h.data(), d_items, n_items * sizeof(double), hipMemcpyDeviceToHost);
-      if (e != hipSuccess) { s = hip_fail(e, "copy pilot sums"); break; }
-      for (size_t i = 0; i < n_items; ++i) {
-        sum[l][i] += h[i];
-        sq[l][i] += h[i] * h[i];
-      }
+      hipError_t e = hipMemcpy(h.data(), c->d_chan_var, nch * sizeof(double), hipMemcpyDeviceToHost);
+      if (e != hipSuccess) { s = hip_fail(e, "copy channel variances"); break; }
+      for (int ci = 0; ci < nch; ++ci) var[l][ci] += h[ci];
     }
   }
   c->step = saved_step;
-  (void)hipFree(d_items);
   if (s) return s;
-  // per channel: summed variance of the item estimates x total pilot time
-  std::vector<uint8_t> flags(std::max(1, c->nch), 1);
-  const double R = n_reps;
+  // per channel: pooled variance of the item estimates x the sampler's pilot time
+  std::vector<uint8_t> flags(nch, 1);
   for (int ci = 0; ci < c->nch; ++ci) {
-    double var[2] = {0.0, 0.0};
-    for (int l = 0; l < 2; ++l)
-      for (int x = 0; x < c->G.cells; ++x)
-        for (int p = 0; p < c->G.nodes; ++p) {
-          const size_t i = ((size_t)x * c->nch + ci) * c->G.nodes + p;
-          const double m = sum[l][i] / R;
-          var[l] += std::max(0.0, (sq[l][i] - R * m * m) / (R - 1.0));
-        }
-    const double cost_u = var[0] * t_ms[0], cost_l = var[1] * t_ms[1];
+    const double cost_u = var[0][ci] * t_ms[0], cost_l = var[1][ci] * t_ms[1];
     flags[ci] = (cost_u > 0.0 && cost_l < cost_u) ? 1 : 0;
     if (ratio) ratio[ci] = cost_u > 0.0 ? cost_l / cost_u : (cost_l > 0.0 ? INFINITY : 1.0);
   }

@@ -38,6 +38,12 @@ METRIC = "collision integrand evals/s + time/step at fixed MC error, plain vs le
 #   interpolations 123, bracket and value 17, three trilinear deposits 66.
 SLOTS_REJECTED = 120 + 20 + 130
 SLOTS_ACCEPTED = SLOTS_REJECTED + 16 + 27 + 123 + 17 + 66
+# The learned sampler adds per evaluation: a second Philox block 120, the
+# mixture draw 110 (Box-Muller: 3 logs, 3 square roots, 3 sin/cos pairs;
+# 5 logistic maps: 5 exponentials, 5 reciprocals; component choice and
+# y = mu + sigma z), the mixture density 210 (8 components x 5 dimensions x
+# 3 ops, 8 exponentials, 5 log-Jacobian terms, one log).
+SLOTS_LEARNED_EXTRA = 120 + 110 + 210
 # MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = one full-rate lane op per slot
 ALU_PEAK_SLOTS = 256 * 64 * 2.4e9
 # LDS: 128 B/clk/CU -> 32 four-byte lane accesses per clock per CU
@@ -290,6 +296,8 @@ def main():
     t_coll = np.array([s["t_collide_ms"] for s in stats]) * 1e-3
     value = evals / elapsed
     slots = SLOTS_ACCEPTED * accepted + SLOTS_REJECTED * (evals - accepted)
+    if sampler == qgbe.SAMPLER_LEARNED:
+        slots += SLOTS_LEARNED_EXTRA * evals
     achieved = slots / t_coll.sum()
     traffic = measured_traffic(wl.name) if a.samples in (0, wl.n_samples) else None
     roof = dict(bound="alu", achieved=achieved, peak=ALU_PEAK_SLOTS, unit="lane-op slots/s",

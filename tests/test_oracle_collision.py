@@ -235,3 +235,31 @@ def test_item_scale_bounds_the_item_sum(O):
     assert np.all(sc >= np.abs(s) * (1 - 1e-14))
     assert sc[empty] > 0 and abs(s[empty] - sc[empty]) <= 1e-13 * sc[empty]
     assert np.array_equal(s, O.item_sums(g, f, m, SEED, 1, 200, items))
+
+
+def test_equilibrium_on_the_grid_is_second_order(O):
+    """Equilibrium f sampled at the nodes: the collision term no longer
+    vanishes, because trilinear interpolation misses f between nodes, and the
+    trilinear deposits move energy by the curvature of E(p) across a cell.
+    Both are second order in dp: the |p|^2 moment of A relative to that of
+    the scale falls as dp^2, the energy moment (the grid's energy
+    non-conservation) at least as fast.  Moments average out the sample noise,
+    whose share from the clamped layer at the box faces (first order, in a
+    layer of width dp/2) would otherwise dominate a pointwise norm."""
+    T, m2 = 0.3, 0.25
+    r_p2, r_E = [], []
+    for n in (10, 20, 40):
+        g = O.Grid(n_p=(n, n, n), p_half=(2.5, 2.5, 2.5), species_mask=1 << G)
+        P = g.momenta()
+        p2 = (P ** 2).sum(1)
+        E = np.sqrt(p2 + m2)
+        f = np.zeros((7, 1, g.nodes))
+        f[G, 0] = 1.0 / np.expm1(E / T)
+        m = np.full((7, 1), m2)
+        A, S, _ = O.collision(g, f, m, SEED, 0, 64)
+        r_p2.append(abs((p2 * A[G, 0]).sum()) / (p2 * S[G, 0]).sum())
+        r_E.append(abs((E * A[G, 0]).sum()) / (E * S[G, 0]).sum())
+    s_p2 = [np.log2(r_p2[i] / r_p2[i + 1]) for i in range(2)]
+    s_E = [np.log2(r_E[i] / r_E[i + 1]) for i in range(2)]
+    assert all(1.6 < x < 2.6 for x in s_p2), (r_p2, s_p2)
+    assert all(x > 1.8 for x in s_E), (r_E, s_E)

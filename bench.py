@@ -166,7 +166,10 @@ def fixed_error(R, epochs):
             return float(np.median([s["t_step_ms"] for s in st[1:]])), float(
                 np.median([s["t_collide_ms"] for s in st[1:]]))
 
-        eps_plain = mc_error(replicas(n_plain, qgbe.SAMPLER_UNIFORM))
+        reps_plain = replicas(n_plain, qgbe.SAMPLER_UNIFORM)
+        eps_plain = mc_error(reps_plain)
+        mean_plain = np.mean(reps_plain, axis=0)
+        del reps_plain
         t_plain, c_plain = step_ms(n_plain, qgbe.SAMPLER_UNIFORM)
         out.update(eps_plain=eps_plain, t_step_plain_ms=t_plain, t_collide_plain_ms=c_plain)
 
@@ -194,11 +197,13 @@ def fixed_error(R, epochs):
         out.update(judge_s=time.perf_counter() - t0, learned_channels=int(flags.sum()),
                    channels=solver.n_channels)
 
-        cache = {}
+        cache, means = {}, {}
 
         def eps_learned(n):
             if n not in cache:
-                cache[n] = mc_error(replicas(n, qgbe.SAMPLER_LEARNED))
+                reps = replicas(n, qgbe.SAMPLER_LEARNED)
+                cache[n] = mc_error(reps)
+                means[n] = np.mean(reps, axis=0)
             return cache[n]
 
         # smallest power of two in [64, n_plain] reaching the plain error, then bisect
@@ -222,6 +227,21 @@ def fixed_error(R, epochs):
                    t_step_learned_ms=t_learned, t_collide_learned_ms=c_learned,
                    time_ratio=t_plain / t_learned,
                    bisection={str(k): v for k, v in sorted(cache.items())})
+        # bias check: both replica means against a plain reference of 16 x 65536 samples
+        solver.set_f(f0)
+        ref_reps = []
+        for r in range(16):
+            qgbe.qgbe_set_step_index(solver.ctx, 5000 + r)
+            ref_reps.append(solver.collision(16 * n_plain)[0])
+        ref = np.mean(ref_reps, axis=0)
+        eps_ref = mc_error(ref_reps) / np.sqrt(16)
+        norm = np.linalg.norm(ref)
+        out["bias_check"] = dict(
+            reference="16 plain replicas x 65536 samples/point",
+            rel_l2_learned=float(np.linalg.norm(means[n_learned] - ref) / norm),
+            rel_l2_plain=float(np.linalg.norm(mean_plain - ref) / norm),
+            expected_learned=float(np.hypot(eps_learned(n_learned) / np.sqrt(R), eps_ref)),
+            expected_plain=float(np.hypot(eps_plain / np.sqrt(R), eps_ref)))
     return out
 
 

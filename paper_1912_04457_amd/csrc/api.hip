@@ -133,18 +133,20 @@ void plan_groups(qgbe_ctx* c) {
   c->group_index.clear();
   c->groups.clear();
   for (int nslot = 1; nslot <= 3; ++nslot) {
-    Group g{(int)c->group_index.size(), 0, nslot, {0, 0}, {0, 0}};
+    Group g{(int)c->group_index.size(), 0, nslot, {0, 0}, {0, 0}, false};
     for (int l = 0; l < 2; ++l) {
       const size_t budget = c->lds_budget[l];
       g.lds_acc[l] = c->d.symmetric ? (int)std::min<size_t>(nslot, budget / acc_b) : 0;
       g.lds_tiles[l] = (int)std::min<size_t>(nslot, (budget - g.lds_acc[l] * acc_b) / tile_b);
     }
+    g.queue = c->d.symmetric && g.lds_acc[0] == nslot && nslot * acc_b <= c->lds_budget_queue;
     for (int i = 0; i < c->nch; ++i)
       if (c->chans[i].nslot == nslot) c->group_index.push_back(i);
     g.count = (int)c->group_index.size() - g.start;
     if (g.count) {
       c->groups.push_back(g);
       for (int l = 0; l < 2; ++l) c->need_quads[l] = c->need_quads[l] || g.lds_tiles[l] < nslot;
+      c->need_quads[0] = c->need_quads[0] || g.queue;
     }
   }
 }
@@ -167,13 +169,15 @@ qgbe_status run_collide(qgbe_ctx* c, int n_samples, bool learned, double* A, dou
     HIP_TRY(launch_collide_f64(a, c->stream), "collide (fp64)");
     return QGBE_OK;
   }
-  const int waves = collide_f32_waves(learned);
   const int l = learned ? 1 : 0;
   if (c->need_quads[l]) HIP_TRY(launch_f32_quads(c->G, c->d_f32, c->d_f32q, c->stream), "f32 quads");
   a.f32q = c->d_f32q;
   for (const Group& g : c->groups) {
     a.group = c->d_groups + g.start;
     a.n_group = g.count;
+    // the compacting variant when the whole group fits in LDS next to its queues
+    const bool queue = !learned && g.queue;
+    const int waves = collide_f32_waves(learned, queue);
     const long long items = (long long)c->G.cells * g.count * c->G.nodes;
     long long chunk = items / 2048;
     chunk = std::max<long long>(waves, std::min<long long>(512, chunk));
@@ -199,7 +203,8 @@ qgbe_status run_collide(qgbe_ctx* c, int n_samples, bool learned, double* A, dou
         const size_t used = (size_t)(a.slot_hi - a.slot_lo) * acc_b;
         a.lds_tiles = (int)std::min<size_t>(g.nslot, (c->lds_budget[l] - used) / tile_b);
       }
-      HIP_TRY(launch_collide_f32(a, g.nslot, c->stream), "collide (fp32)");
+      if (queue) a.lds_tiles = 0;  // the compacting variant reads f from the node quads
+      HIP_TRY(launch_collide_f32(a, g.nslot, queue && n_pass == 1, c->stream), "collide (fp32)");
     }
   }
   return QGBE_OK;
@@ -293,8 +298,8 @@ qgbe_status qgbe_init_grid(const qgbe_grid_desc* desc, qgbe_ctx** out) {
   int lds_max = 0;
   HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, desc->device),
           "query LDS size");
-  size_t lds_budget[2] = {0, 0};
-  HIP_TRY(set_collide_lds_limit((size_t)std::max(lds_max, 0), &lds_budget[0], &lds_budget[1]),
+  size_t lds_budget[3] = {0, 0, 0};
+  HIP_TRY(set_collide_lds_limit((size_t)std::max(lds_max, 0), &lds_budget[0], &lds_budget[1], &lds_budget[2]),
           "raise the dynamic LDS limit");
   qgbe_ctx* c = new qgbe_ctx();
   c->d = *desc;
@@ -305,6 +310,7 @@ qgbe_status qgbe_init_grid(const qgbe_grid_desc* desc, qgbe_ctx** out) {
   c->chans.resize(c->nch);
   c->lds_budget[0] = lds_budget[0];
   c->lds_budget[1] = lds_budget[1];
+  c->lds_budget_queue = lds_budget[2];
   plan_groups(c);
   const size_t n = field_len(c);
   std::vector<int> all(std::max(1, c->nch));

@@ -41,13 +41,15 @@ struct CollideArgs {
 };
 
 hipError_t launch_collide_f64(const CollideArgs& a, hipStream_t stream);
-hipError_t launch_collide_f32(const CollideArgs& a, int nslot, hipStream_t stream);
+// queue: use the compacting variant if the launch qualifies (uniform sampler,
+// symmetric, every tile and accumulator in LDS within the queue budget).
+hipError_t launch_collide_f32(const CollideArgs& a, int nslot, bool queue, hipStream_t stream);
 // Raise the FP32 kernels' dynamic LDS limit to what their static LDS leaves
-// of lds_max; returns the dynamic budget of the uniform-sampler and of the
-// learned-sampler variants.
-hipError_t set_collide_lds_limit(size_t lds_max, size_t* budget_plain, size_t* budget_learned);
+// of lds_max; returns the dynamic budget of the uniform-sampler, the
+// learned-sampler and the compacting variants.
+hipError_t set_collide_lds_limit(size_t lds_max, size_t* budget_plain, size_t* budget_learned, size_t* budget_queue);
 // Waves per workgroup of the FP32 kernel (chunks are multiples of it).
-int collide_f32_waves(bool learned);
+int collide_f32_waves(bool learned, bool queue);
 hipError_t launch_record(const CollideArgs& a, int n_per_item, long long item_stride, long long n_sel, float* rows,
                          hipStream_t stream);
 

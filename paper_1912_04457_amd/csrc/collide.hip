@@ -316,6 +316,14 @@ __device__ __forceinline__ void five_uniforms(uint32_t x0, uint32_t x1, uint32_t
   u[4] = unif23(((x0 & 0x1FFu) << 14) | ((x1 & 0x1FFu) << 5) | ((x2 & 0x1FFu) >> 4));
 }
 
+// Order a wave's LDS accesses across its lanes (the LDS executes one wave's
+// instructions in order; this keeps the compiler from reordering them).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ int wave_count(int v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
@@ -507,12 +515,17 @@ __device__ __forceinline__ void load_item(Item& it, const CollideArgs& A, const 
 }
 
 
-// Per-sample value (without the bracket) and the bracket, in precision R.
+// Per-sample value without the bracket, in precision R: |M|^2 times the
+// phase-space prefactor.
+template <typename R>
+__device__ __forceinline__ R prefactor(const Item& it, const Geo& g) {
+  return (R)it.pref * (R)g.pstar * (R)g.rs * rcp_r<R>((R)g.E2);
+}
+
 template <typename R>
 __device__ __forceinline__ R weight_no_bracket(const Item& it, const Geo& g, int row) {
   const R m = matrix_element<R>(row, (R)g.s, (R)g.t, (R)g.u, (R)it.mu);
-  const R pre = (R)it.pref * (R)g.pstar * (R)g.rs * rcp_r<R>((R)g.E2);
-  return m * pre;
+  return m * prefactor<R>(it, g);
 }
 
 __device__ __forceinline__ bool is_gluon(int sp) { return sp == kGluon; }
@@ -687,11 +700,27 @@ __device__ __forceinline__ void deposit_slot(int k, int slot_lo, int slot_hi, in
 // VGPRs; the learned variant spills a few to scratch and still runs faster
 // than with 8 waves).
 constexpr int f32_threads(bool learned) { return learned ? 768 : 768; }
+// The compacting variant (below) keeps a sample queue per wave in LDS next
+// to the accumulators and reads f from the global node quads.
+constexpr int kQueueWaves = 12;
+constexpr int kQueueLen = 128;  // ring entries per wave (>= 63 pending + 64 new)
+constexpr int f32_block(bool learned, bool queue) { return queue ? kQueueWaves * 64 : f32_threads(learned); }
 
-template <bool kSym, bool kScale, bool kAllLds, bool kLearned>
-__global__ __launch_bounds__(f32_threads(kLearned)) void collide_f32_kernel(CollideArgs A) {
+// kQueue (uniform sampler, every deposit slot in LDS, f from the global node
+// quads): each wave first runs the sample geometry for 64 samples, appends
+// the accepted ones (the three 23-bit uniforms of p2, p3 in FP64, s, t, u and
+// the prefactor in FP32) to its ring in LDS, and evaluates integrand and
+// deposits 64 queued samples at a time, so that long path runs on full
+// wavefronts.  Same arithmetic per sample as the direct loop.
+template <bool kSym, bool kScale, bool kAllLds, bool kLearned, bool kQueue>
+__global__ __launch_bounds__(f32_block(kLearned, kQueue)) void collide_f32_kernel(CollideArgs A) {
+  static_assert(!kQueue || (kSym && kAllLds && !kLearned), "the queue serves the uniform sampler, slots in LDS");
+  constexpr bool kTilesLds = kAllLds && !kQueue;  // every f tile in LDS (the queue variant reads quads)
   extern __shared__ double lds[];
   __shared__ float mix_rows[kLearned ? f32_threads(true) / kWave : 1][kLearned ? kMixRow : 1];
+  __shared__ uint32_t q_v[kQueue ? kQueueWaves : 1][3][kQueue ? kQueueLen : 1];  // 23-bit uniforms of p2
+  __shared__ double q_p3[kQueue ? kQueueWaves : 1][3][kQueue ? kQueueLen : 1];
+  __shared__ float q_f[kQueue ? kQueueWaves : 1][4][kQueue ? kQueueLen : 1];    // s, t, u, prefactor
   __shared__ double mc_wg[2];  // this workgroup's item variances and squared item sums
   const Grid& G = A.G;
   const int lane = threadIdx.x & (kWave - 1);
@@ -747,17 +776,15 @@ __global__ __launch_bounds__(f32_threads(kLearned)) void collide_f32_kernel(Coll
     }
     // One sample from its five uniforms: FP64 geometry (the decision), FP32
     // integrand, direct sum and deposits.
-    auto evaluate = [&](const double u[5], float inv_q) {
-      Geo g;
-      if (!geometry(it, G, u, g)) return;
+    // integrand and deposits of an accepted sample (wnb = value without bracket)
+    auto finish = [&](const Geo& g, float wnb) {
       ++n_ok;
-      const float wnb = weight_no_bracket<float>(it, g, ch.row) * inv_q;
       const Stencil<float> s2 = make_stencil<float>(g.p2, G);
       const Stencil<float> s3 = make_stencil<float>(g.p3, G);
       const Stencil<float> s4 = make_stencil<float>(g.p4, G);
-      const float f2 = interp_slot<kAllLds, float>(k2, n_tiles, tiles, A.f32q, off2, s2, nodes, G.ox, G.oy);
-      const float f3 = interp_slot<kAllLds, float>(k3, n_tiles, tiles, A.f32q, off3, s3, nodes, G.ox, G.oy);
-      const float f4 = interp_slot<kAllLds, float>(k4, n_tiles, tiles, A.f32q, off4, s4, nodes, G.ox, G.oy);
+      const float f2 = interp_slot<kTilesLds, float>(k2, n_tiles, tiles, A.f32q, off2, s2, nodes, G.ox, G.oy);
+      const float f3 = interp_slot<kTilesLds, float>(k3, n_tiles, tiles, A.f32q, off3, s3, nodes, G.ox, G.oy);
+      const float f4 = interp_slot<kTilesLds, float>(k4, n_tiles, tiles, A.f32q, off4, s4, nodes, G.ox, G.oy);
       const float F2 = g2 ? 1.0f + f2 : 1.0f - f2;
       const float F3 = g3 ? 1.0f + f3 : 1.0f - f3;
       const float F4 = g4 ? 1.0f + f4 : 1.0f - f4;
@@ -778,6 +805,61 @@ __global__ __launch_bounds__(f32_threads(kLearned)) void collide_f32_kernel(Coll
         }
       }
     };
+    auto evaluate = [&](const double u[5], float inv_q) {
+      Geo g;
+      if (!geometry(it, G, u, g)) return;
+      finish(g, weight_no_bracket<float>(it, g, ch.row) * inv_q);
+    };
+    if (kQueue) {
+      // queued record -> the accepted sample's geometry, as geometry() left it
+      auto finish_queued = [&](int slot) {
+        Geo g;
+        const uint32_t v0 = q_v[wid][0][slot], v1 = q_v[wid][1][slot], v2 = q_v[wid][2][slot];
+        const double uu[3] = {unif23(v0), unif23(v1), unif23(v2)};
+        for (int a = 0; a < 3; ++a) {
+          g.p2[a] = fma(2.0 * G.ph[a], uu[a], -G.ph[a]);
+          g.p3[a] = q_p3[wid][a][slot];
+          g.p4[a] = (it.p1[a] + g.p2[a]) - g.p3[a];
+        }
+        const float m = matrix_element<float>(ch.row, q_f[wid][0][slot], q_f[wid][1][slot], q_f[wid][2][slot],
+                                              (float)it.mu);
+        finish(g, m * q_f[wid][3][slot]);
+      };
+      unsigned head = 0, tail = 0;  // ring positions (wave-uniform)
+      for (int base = 0; base < A.n_samples; base += kWave) {
+        const int s = base + lane;
+        uint32_t x0 = (uint32_t)s, x1 = (uint32_t)p1_lin, x2 = (uint32_t)cell, x3 = ((uint32_t)ch.code << 8);
+        philox4x32_10(x0, x1, x2, x3, A.key0, A.key1);
+        double u[5];
+        five_uniforms(x0, x1, x2, x3, u);
+        Geo g;
+        const bool ok = s < A.n_samples && geometry(it, G, u, g);
+        const unsigned long long mask = __ballot(ok);
+        if (ok) {
+          const unsigned slot = (tail + (unsigned)__popcll(mask & ((1ull << lane) - 1ull))) & (kQueueLen - 1);
+          q_v[wid][0][slot] = x0 >> 9;
+          q_v[wid][1][slot] = x1 >> 9;
+          q_v[wid][2][slot] = x2 >> 9;
+          for (int a = 0; a < 3; ++a) q_p3[wid][a][slot] = g.p3[a];
+          q_f[wid][0][slot] = (float)g.s;
+          q_f[wid][1][slot] = (float)g.t;
+          q_f[wid][2][slot] = (float)g.u;
+          q_f[wid][3][slot] = prefactor<float>(it, g);
+        }
+        tail += (unsigned)__popcll(mask);
+        if (tail - head >= (unsigned)kWave) {
+          wave_lds_sync();
+          finish_queued((head + lane) & (kQueueLen - 1));
+          head += kWave;
+          wave_lds_sync();
+        }
+      }
+      if (tail != head) {  // the last, partial batch
+        wave_lds_sync();
+        if ((unsigned)lane < tail - head) finish_queued((head + lane) & (kQueueLen - 1));
+        wave_lds_sync();
+      }
+    } else
     for (int s = lane; s < A.n_samples; s += kWave) {
       uint32_t x0 = (uint32_t)s, x1 = (uint32_t)p1_lin, x2 = (uint32_t)cell, x3 = ((uint32_t)ch.code << 8);
       philox4x32_10(x0, x1, x2, x3, A.key0, A.key1);
@@ -910,73 +992,95 @@ hipError_t launch_collide_f64(const CollideArgs& a, hipStream_t stream) {
 }
 
 template <bool kSym, bool kScale, bool kLearned>
-void launch_f32_variant(const CollideArgs& a, bool all_lds, dim3 grid, dim3 block, size_t lds, hipStream_t st) {
+void launch_f32_variant(const CollideArgs& a, bool all_lds, bool queue, dim3 grid, dim3 block, size_t lds,
+                        hipStream_t st) {
+  if constexpr (kSym && !kLearned) {
+    if (queue) {
+      hipLaunchKernelGGL((collide_f32_kernel<true, kScale, true, false, true>), grid, block, lds, st, a);
+      return;
+    }
+  }
   if (all_lds)
-    hipLaunchKernelGGL((collide_f32_kernel<kSym, kScale, true, kLearned>), grid, block, lds, st, a);
+    hipLaunchKernelGGL((collide_f32_kernel<kSym, kScale, true, kLearned, false>), grid, block, lds, st, a);
   else
-    hipLaunchKernelGGL((collide_f32_kernel<kSym, kScale, false, kLearned>), grid, block, lds, st, a);
+    hipLaunchKernelGGL((collide_f32_kernel<kSym, kScale, false, kLearned, false>), grid, block, lds, st, a);
 }
 
 template <bool kSym, bool kScale>
-void launch_f32_sampler(const CollideArgs& a, bool all_lds, dim3 grid, dim3 block, size_t lds, hipStream_t st) {
-  if (a.learned) launch_f32_variant<kSym, kScale, true>(a, all_lds, grid, block, lds, st);
-  else launch_f32_variant<kSym, kScale, false>(a, all_lds, grid, block, lds, st);
+void launch_f32_sampler(const CollideArgs& a, bool all_lds, bool queue, dim3 grid, dim3 block, size_t lds,
+                        hipStream_t st) {
+  if (a.learned) launch_f32_variant<kSym, kScale, true>(a, all_lds, false, grid, block, lds, st);
+  else launch_f32_variant<kSym, kScale, false>(a, all_lds, queue, grid, block, lds, st);
 }
 
-int collide_f32_waves(bool learned) { return f32_threads(learned) / kWave; }
+int collide_f32_waves(bool learned, bool queue) { return f32_block(learned, queue) / kWave; }
 
-hipError_t launch_collide_f32(const CollideArgs& a, int nslot, hipStream_t stream) {
-  const int threads = f32_threads(a.learned != 0);
+hipError_t launch_collide_f32(const CollideArgs& a, int nslot, bool queue, hipStream_t stream) {
   const int n_acc = a.symmetric ? std::min(a.slot_hi - a.slot_lo, a.lds_acc) : 0;
   const int n_tiles = std::min(nslot, a.lds_tiles);
   // every tile and every accumulator of this launch's slots in LDS: the
   // variant without global-memory paths
-  const bool all_lds = n_tiles == nslot && (!a.symmetric || n_acc == a.slot_hi - a.slot_lo);
+  const bool all_acc = !a.symmetric || n_acc == a.slot_hi - a.slot_lo;
+  const bool all_lds = n_tiles == nslot && all_acc;
+  queue = queue && all_acc && a.symmetric && !a.learned;
+  const int threads = f32_block(a.learned != 0, queue);
   const size_t lds = (size_t)n_acc * a.G.nodes * sizeof(double) + (size_t)n_tiles * a.G.nodes * sizeof(float);
   const long long blocks = (long long)a.G.cells * a.n_group * a.n_chunks;
   if (blocks <= 0) return hipSuccess;
   const dim3 grid((unsigned)blocks), block(threads);
   if (a.symmetric) {
-    if (a.scale) launch_f32_sampler<true, true>(a, all_lds, grid, block, lds, stream);
-    else launch_f32_sampler<true, false>(a, all_lds, grid, block, lds, stream);
+    if (a.scale) launch_f32_sampler<true, true>(a, all_lds, queue, grid, block, lds, stream);
+    else launch_f32_sampler<true, false>(a, all_lds, queue, grid, block, lds, stream);
   } else {
-    if (a.scale) launch_f32_sampler<false, true>(a, all_lds, grid, block, lds, stream);
-    else launch_f32_sampler<false, false>(a, all_lds, grid, block, lds, stream);
+    if (a.scale) launch_f32_sampler<false, true>(a, all_lds, false, grid, block, lds, stream);
+    else launch_f32_sampler<false, false>(a, all_lds, false, grid, block, lds, stream);
   }
   return hipGetLastError();
 }
 
-hipError_t set_collide_lds_limit(size_t lds_max, size_t* budget_plain, size_t* budget_learned) {
+hipError_t set_collide_lds_limit(size_t lds_max, size_t* budget_plain, size_t* budget_learned, size_t* budget_queue) {
   // Each FP32 variant may use what its static LDS leaves of lds_max.  Raising
   // the per-kernel dynamic limit is only needed (and only accepted) above the
   // runtime's default; after a refusal the budget is the limit in force.
-  const void* fns[16] = {
-      (const void*)collide_f32_kernel<true, true, true, false>,   (const void*)collide_f32_kernel<true, false, true, false>,
-      (const void*)collide_f32_kernel<false, true, true, false>,  (const void*)collide_f32_kernel<false, false, true, false>,
-      (const void*)collide_f32_kernel<true, true, false, false>,  (const void*)collide_f32_kernel<true, false, false, false>,
-      (const void*)collide_f32_kernel<false, true, false, false>, (const void*)collide_f32_kernel<false, false, false, false>,
-      (const void*)collide_f32_kernel<true, true, true, true>,    (const void*)collide_f32_kernel<true, false, true, true>,
-      (const void*)collide_f32_kernel<false, true, true, true>,   (const void*)collide_f32_kernel<false, false, true, true>,
-      (const void*)collide_f32_kernel<true, true, false, true>,   (const void*)collide_f32_kernel<true, false, false, true>,
-      (const void*)collide_f32_kernel<false, true, false, true>,  (const void*)collide_f32_kernel<false, false, false, true>};
-  size_t budget[2] = {lds_max, lds_max};
-  for (int i = 0; i < 16; ++i) {
+  // Groups: 0 uniform sampler, 1 learned sampler, 2 the compacting variant.
+  struct Fn { const void* fn; int group; };
+  const Fn fns[18] = {
+      {(const void*)collide_f32_kernel<true, true, true, false, false>, 0},
+      {(const void*)collide_f32_kernel<true, false, true, false, false>, 0},
+      {(const void*)collide_f32_kernel<false, true, true, false, false>, 0},
+      {(const void*)collide_f32_kernel<false, false, true, false, false>, 0},
+      {(const void*)collide_f32_kernel<true, true, false, false, false>, 0},
+      {(const void*)collide_f32_kernel<true, false, false, false, false>, 0},
+      {(const void*)collide_f32_kernel<false, true, false, false, false>, 0},
+      {(const void*)collide_f32_kernel<false, false, false, false, false>, 0},
+      {(const void*)collide_f32_kernel<true, true, true, true, false>, 1},
+      {(const void*)collide_f32_kernel<true, false, true, true, false>, 1},
+      {(const void*)collide_f32_kernel<false, true, true, true, false>, 1},
+      {(const void*)collide_f32_kernel<false, false, true, true, false>, 1},
+      {(const void*)collide_f32_kernel<true, true, false, true, false>, 1},
+      {(const void*)collide_f32_kernel<true, false, false, true, false>, 1},
+      {(const void*)collide_f32_kernel<false, true, false, true, false>, 1},
+      {(const void*)collide_f32_kernel<false, false, false, true, false>, 1},
+      {(const void*)collide_f32_kernel<true, true, true, false, true>, 2},
+      {(const void*)collide_f32_kernel<true, false, true, false, true>, 2}};
+  size_t budget[3] = {lds_max, lds_max, lds_max};
+  for (const Fn& f : fns) {
     hipFuncAttributes attr;
-    if (hipFuncGetAttributes(&attr, fns[i]) != hipSuccess) return hipGetLastError();
+    if (hipFuncGetAttributes(&attr, f.fn) != hipSuccess) return hipGetLastError();
     const size_t stat = attr.sharedSizeBytes;
     size_t want = lds_max > stat ? lds_max - stat : 0;
     size_t have = attr.maxDynamicSharedSizeBytes > 0 ? (size_t)attr.maxDynamicSharedSizeBytes : 0;
     if (have < want) {
-      if (hipFuncSetAttribute(fns[i], hipFuncAttributeMaxDynamicSharedMemorySize, (int)want) == hipSuccess)
+      if (hipFuncSetAttribute(f.fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)want) == hipSuccess)
         have = want;
       else
         (void)hipGetLastError();
     }
-    size_t& b = budget[i >= 8 ? 1 : 0];
-    b = std::min(b, std::min(have, want));
+    budget[f.group] = std::min(budget[f.group], std::min(have, want));
   }
   *budget_plain = budget[0];
   *budget_learned = budget[1];
+  *budget_queue = budget[2];
   return hipSuccess;
 }
 

@@ -29,6 +29,7 @@ struct Group {
   int nslot;          // distinct species at positions 2..4
   int lds_acc[2];     // FP64 accumulators staged in LDS  [uniform, learned sampler]
   int lds_tiles[2];   // FP32 f tiles staged in LDS       [uniform, learned sampler]
+  bool queue;         // the uniform sampler's compacting variant fits
 };
 
 // Device buffers of the proposal network (allocated on first use).
@@ -87,6 +88,7 @@ struct qgbe_ctx {
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   size_t ws = 0;
   size_t lds_budget[2] = {0, 0};   // dynamic LDS per workgroup [uniform, learned sampler]
+  size_t lds_budget_queue = 0;     // dynamic LDS of the compacting uniform-sampler variant
 };
 
 namespace qgbe {

@@ -146,7 +146,7 @@ void plan_groups(qgbe_ctx* c) {
     if (g.count) {
       c->groups.push_back(g);
       for (int l = 0; l < 2; ++l) c->need_quads[l] = c->need_quads[l] || g.lds_tiles[l] < nslot;
-      c->need_quads[0] = c->need_quads[0] || g.queue;
+      c->need_quads[0] = c->need_quads[0] || (g.queue && nslot * (acc_b + tile_b) > c->lds_budget_queue);
     }
   }
 }
@@ -203,7 +203,8 @@ qgbe_status run_collide(qgbe_ctx* c, int n_samples, bool learned, double* A, dou
         const size_t used = (size_t)(a.slot_hi - a.slot_lo) * acc_b;
         a.lds_tiles = (int)std::min<size_t>(g.nslot, (c->lds_budget[l] - used) / tile_b);
       }
-      if (queue) a.lds_tiles = 0;  // the compacting variant reads f from the node quads
+      if (queue)  // tiles in what the queues leave, the rest from the node quads
+        a.lds_tiles = (int)std::min<size_t>(g.nslot, (c->lds_budget_queue - g.nslot * acc_b) / tile_b);
       HIP_TRY(launch_collide_f32(a, g.nslot, queue && n_pass == 1, c->stream), "collide (fp32)");
     }
   }

@@ -700,27 +700,31 @@ __device__ __forceinline__ void deposit_slot(int k, int slot_lo, int slot_hi, in
 // VGPRs; the learned variant spills a few to scratch and still runs faster
 // than with 8 waves).
 constexpr int f32_threads(bool learned) { return learned ? 768 : 768; }
-// The compacting variant (below) keeps a sample queue per wave in LDS next
-// to the accumulators and reads f from the global node quads.
+// The compacting variant (below) keeps a sample queue per wave in LDS (40 B
+// per entry) next to the accumulators and, where they fit, the f tiles.
 constexpr int kQueueWaves = 12;
 constexpr int kQueueLen = 128;  // ring entries per wave (>= 63 pending + 64 new)
 constexpr int f32_block(bool learned, bool queue) { return queue ? kQueueWaves * 64 : f32_threads(learned); }
 
-// kQueue (uniform sampler, every deposit slot in LDS, f from the global node
-// quads): each wave first runs the sample geometry for 64 samples, appends
-// the accepted ones (the three 23-bit uniforms of p2, p3 in FP64, s, t, u and
-// the prefactor in FP32) to its ring in LDS, and evaluates integrand and
-// deposits 64 queued samples at a time, so that long path runs on full
-// wavefronts.  Same arithmetic per sample as the direct loop.
+// kQueue (uniform sampler, every deposit slot in LDS; f tiles in LDS with
+// kAllLds, else from the global node quads): each wave first runs the sample
+// geometry and |M|^2 for 64 samples, appends the accepted ones (the three
+// 23-bit uniforms of p2, p3 in FP64, the value without the bracket in FP32)
+// to its ring in LDS, and evaluates f, bracket and deposits 64 queued samples
+// at a time, so that long path runs on full wavefronts.  Same arithmetic per
+// sample as the direct loop.
 template <bool kSym, bool kScale, bool kAllLds, bool kLearned, bool kQueue>
 __global__ __launch_bounds__(f32_block(kLearned, kQueue)) void collide_f32_kernel(CollideArgs A) {
-  static_assert(!kQueue || (kSym && kAllLds && !kLearned), "the queue serves the uniform sampler, slots in LDS");
-  constexpr bool kTilesLds = kAllLds && !kQueue;  // every f tile in LDS (the queue variant reads quads)
+  static_assert(!kQueue || (kSym && !kLearned), "the queue serves the symmetric uniform sampler");
+  // kAllLds: every f tile in LDS (and every accumulator; the queue variant
+  // always keeps its accumulators in LDS)
+  constexpr bool kTilesLds = kAllLds;
+  constexpr bool kAccLds = kAllLds || kQueue;
   extern __shared__ double lds[];
   __shared__ float mix_rows[kLearned ? f32_threads(true) / kWave : 1][kLearned ? kMixRow : 1];
   __shared__ uint32_t q_v[kQueue ? kQueueWaves : 1][3][kQueue ? kQueueLen : 1];  // 23-bit uniforms of p2
   __shared__ double q_p3[kQueue ? kQueueWaves : 1][3][kQueue ? kQueueLen : 1];
-  __shared__ float q_f[kQueue ? kQueueWaves : 1][4][kQueue ? kQueueLen : 1];    // s, t, u, prefactor
+  __shared__ float q_w[kQueue ? kQueueWaves : 1][kQueue ? kQueueLen : 1];       // value without bracket
   __shared__ double mc_wg[2];  // this workgroup's item variances and squared item sums
   const Grid& G = A.G;
   const int lane = threadIdx.x & (kWave - 1);
@@ -794,9 +798,9 @@ __global__ __launch_bounds__(f32_block(kLearned, kQueue)) void collide_f32_kerne
       dsq = fma((double)v, (double)v, dsq);
       if (kScale) ssum += (double)(fabsf(wnb) * (gain + loss));
       if (kSym) {
-        deposit_slot<kAllLds>(k2, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off2, s2, v, nodes, G.ox, G.oy);
-        deposit_slot<kAllLds>(k3, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off3, s3, -v, nodes, G.ox, G.oy);
-        deposit_slot<kAllLds>(k4, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off4, s4, -v, nodes, G.ox, G.oy);
+        deposit_slot<kAccLds>(k2, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off2, s2, v, nodes, G.ox, G.oy);
+        deposit_slot<kAccLds>(k3, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off3, s3, -v, nodes, G.ox, G.oy);
+        deposit_slot<kAccLds>(k4, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off4, s4, -v, nodes, G.ox, G.oy);
         if (kScale && A.direct) {
           const float vs = fabsf(wnb) * (gain + loss);
           deposit<double, double>(A.scale + ((size_t)ch.sp[1] * G.cells + cell) * nodes, widen(s2), (double)vs, G.ox, G.oy);
@@ -821,9 +825,7 @@ __global__ __launch_bounds__(f32_block(kLearned, kQueue)) void collide_f32_kerne
           g.p3[a] = q_p3[wid][a][slot];
           g.p4[a] = (it.p1[a] + g.p2[a]) - g.p3[a];
         }
-        const float m = matrix_element<float>(ch.row, q_f[wid][0][slot], q_f[wid][1][slot], q_f[wid][2][slot],
-                                              (float)it.mu);
-        finish(g, m * q_f[wid][3][slot]);
+        finish(g, q_w[wid][slot]);
       };
       unsigned head = 0, tail = 0;  // ring positions (wave-uniform)
       for (int base = 0; base < A.n_samples; base += kWave) {
@@ -841,10 +843,7 @@ __global__ __launch_bounds__(f32_block(kLearned, kQueue)) void collide_f32_kerne
           q_v[wid][1][slot] = x1 >> 9;
           q_v[wid][2][slot] = x2 >> 9;
           for (int a = 0; a < 3; ++a) q_p3[wid][a][slot] = g.p3[a];
-          q_f[wid][0][slot] = (float)g.s;
-          q_f[wid][1][slot] = (float)g.t;
-          q_f[wid][2][slot] = (float)g.u;
-          q_f[wid][3][slot] = prefactor<float>(it, g);
+          q_w[wid][slot] = weight_no_bracket<float>(it, g, ch.row);
         }
         tail += (unsigned)__popcll(mask);
         if (tail - head >= (unsigned)kWave) {
@@ -996,7 +995,10 @@ void launch_f32_variant(const CollideArgs& a, bool all_lds, bool queue, dim3 gri
                         hipStream_t st) {
   if constexpr (kSym && !kLearned) {
     if (queue) {
-      hipLaunchKernelGGL((collide_f32_kernel<true, kScale, true, false, true>), grid, block, lds, st, a);
+      if (all_lds)
+        hipLaunchKernelGGL((collide_f32_kernel<true, kScale, true, false, true>), grid, block, lds, st, a);
+      else
+        hipLaunchKernelGGL((collide_f32_kernel<true, kScale, false, false, true>), grid, block, lds, st, a);
       return;
     }
   }
@@ -1044,7 +1046,7 @@ hipError_t set_collide_lds_limit(size_t lds_max, size_t* budget_plain, size_t* b
   // runtime's default; after a refusal the budget is the limit in force.
   // Groups: 0 uniform sampler, 1 learned sampler, 2 the compacting variant.
   struct Fn { const void* fn; int group; };
-  const Fn fns[18] = {
+  const Fn fns[20] = {
       {(const void*)collide_f32_kernel<true, true, true, false, false>, 0},
       {(const void*)collide_f32_kernel<true, false, true, false, false>, 0},
       {(const void*)collide_f32_kernel<false, true, true, false, false>, 0},
@@ -1062,7 +1064,9 @@ hipError_t set_collide_lds_limit(size_t lds_max, size_t* budget_plain, size_t* b
       {(const void*)collide_f32_kernel<false, true, false, true, false>, 1},
       {(const void*)collide_f32_kernel<false, false, false, true, false>, 1},
       {(const void*)collide_f32_kernel<true, true, true, false, true>, 2},
-      {(const void*)collide_f32_kernel<true, false, true, false, true>, 2}};
+      {(const void*)collide_f32_kernel<true, false, true, false, true>, 2},
+      {(const void*)collide_f32_kernel<true, true, false, false, true>, 2},
+      {(const void*)collide_f32_kernel<true, false, false, false, true>, 2}};
   size_t budget[3] = {lds_max, lds_max, lds_max};
   for (const Fn& f : fns) {
     hipFuncAttributes attr;

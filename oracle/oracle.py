@@ -335,6 +335,57 @@ def observables(grid: Grid, f, mass2) -> dict:
     return dict(N=N, E=E, P=P, N_total=float(N.sum()), E_total=float(E.sum()))
 
 
+def _cell_measure(grid: Grid) -> float:
+    """dV_x dV_p / (2 pi)^3 of one phase-space cell."""
+    dx = np.prod([2.0 * h / n for n, h in zip(grid.n_x, grid.x_half)])
+    dp = np.prod([2.0 * h / n for n, h in zip(grid.n_p, grid.p_half)])
+    return float(dx * dp / (2.0 * np.pi) ** 3)
+
+
+def _energies(grid: Grid, mass2) -> np.ndarray:
+    """E = sqrt(p^2 + m^2) on every (species, cell, node), shape (7, cells, nodes)."""
+    p2 = (grid.momenta() ** 2).sum(axis=1)
+    return np.sqrt(p2[None, None, :] + _mass(grid, mass2)[:, :, None])
+
+
+def energy_budget(grid: Grid, f, A, mass2, mass2_prev, dt_fm: float) -> dict:
+    """Energy bookkeeping of one step taken from f with masses mass2.
+
+    Eq. current conservation gives the kinetic tensor a source S_ex^0 from the
+    time dependence of the masses; over one step, at fixed f, its integral is
+    the change of sum N dV E f when E = sqrt(p^2 + m^2) moves from the previous
+    masses to the current ones (``E_source``; 0 without previous masses).  The
+    collision term changes f by dt A / (N hbar c), i.e. the energy by
+    ``E_collide`` = dt / (hbar c) sum dV E A over evolved species, which the
+    paper shows is not exactly zero on a grid (Sec. IV, energy test).
+    """
+    f = _field(grid, f)
+    A = _field(grid, A)
+    meas = _cell_measure(grid)
+    E = _energies(grid, mass2)
+    if mass2_prev is None:
+        src = 0.0
+    else:
+        dE = E - _energies(grid, mass2_prev)
+        src = float((DEGENERACY[:, None, None] * f * dE).sum() * meas)
+    evolve = np.array([(grid.species_mask >> sp) & 1 for sp in range(7)], dtype=bool)
+    col = float((E * A)[evolve].sum() * meas * dt_fm / HBARC)
+    return dict(E_source=src, E_collide=col)
+
+
+def modified_energy(grid: Grid, f, mass2) -> float:
+    """T^00 of the modified tensor of Sec. IV: T_kin^00 - 1/4 sum N dV m^2 f / E
+    (a massless p = 0 node contributes nothing)."""
+    f = _field(grid, f)
+    m2 = _mass(grid, mass2)[:, :, None]
+    E = _energies(grid, mass2)
+    meas = _cell_measure(grid)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        term = np.where(E > 0.0, m2 * f / np.where(E > 0.0, E, 1.0), 0.0)
+    T = (DEGENERACY[:, None, None] * E * f).sum() * meas
+    return float(T - 0.25 * (DEGENERACY[:, None, None] * term).sum() * meas)
+
+
 @dataclass
 class State:
     """Evolving state of the oracle's time stepper."""
@@ -354,6 +405,7 @@ def step(grid: Grid, state: State, dt_fm: float, n_samples: int, seed: int, *,
         m2 = masses(grid, state.f, state.mass2_lag)
     A, _, _ = collision(grid, state.f, m2, seed, state.step, n_samples, symmetric=symmetric,
                         want_scale=False, threads=threads)
+    budget = energy_budget(grid, state.f, A, m2, state.mass2_lag, dt_fm)
     D = drift(grid, state.f, m2, scheme)
     evolve = np.array([(grid.species_mask >> sp) & 1 for sp in range(7)], dtype=bool)
     upd = dt_fm * (A / (DEGENERACY[:, None, None] * HBARC) - D)
@@ -363,5 +415,7 @@ def step(grid: Grid, state: State, dt_fm: float, n_samples: int, seed: int, *,
     state.step += 1
     obs = observables(grid, state.f, m2)
     obs["mass2"] = m2
+    obs.update(budget)
+    obs["E_total_mod"] = modified_energy(grid, state.f, m2)
     state.history.append(obs)
     return obs

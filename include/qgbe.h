@@ -109,6 +109,24 @@ typedef struct {
                               item's sum of N sample values, Var S_i =
                               N/(N-1) (sum v^2 - S_i^2/N); infinite when
                               Q <= V (the sums are noise)                     */
+  /* Energy bookkeeping of a step (Eq. current conservation and the modified
+   * tensor of Sec. IV, energy test), all integrated over the box, in GeV.
+   * With f_k the field the step starts from, m_k^2 its masses and m_{k-1}^2
+   * those of the step before:
+   *   E_source  = sum over species, cells, nodes of N dV f_k (E(m_k^2) -
+   *               E(m_{k-1}^2)): the kinetic-energy change that the mass
+   *               change alone causes at fixed f (the integral of S_ex^0 over
+   *               the step); 0 on a first step and with constant masses.
+   *   E_collide = dt/(hbar c) sum dV E(m_k^2) A over evolved species: the
+   *               energy the collision term adds (zero in the continuum; the
+   *               grid leaves a residue).
+   * so that E_total(k) - E_total(k-1) = E_source + E_collide + the drift's
+   * part.  E_total_mod = E_total - 1/4 sum N dV m^2 f / E, T^00 of the
+   * modified tensor (conserved for a single species, Sec. IV).  qgbe_step
+   * fills E_source and E_collide; other calls leave them 0.                  */
+  double E_source;
+  double E_collide;
+  double E_total_mod;
 } qgbe_stats;
 
 /* Optional outputs of the collision term (all may be NULL). */

@@ -146,7 +146,7 @@ void plan_groups(qgbe_ctx* c) {
     if (g.count) {
       c->groups.push_back(g);
       for (int l = 0; l < 2; ++l) c->need_quads[l] = c->need_quads[l] || g.lds_tiles[l] < nslot;
-      c->need_quads[0] = c->need_quads[0] || (g.queue && nslot * (acc_b + tile_b) > c->lds_budget_queue);
+      c->need_quads[0] = c->need_quads[0] || g.queue;
     }
   }
 }
@@ -203,8 +203,7 @@ qgbe_status run_collide(qgbe_ctx* c, int n_samples, bool learned, double* A, dou
         const size_t used = (size_t)(a.slot_hi - a.slot_lo) * acc_b;
         a.lds_tiles = (int)std::min<size_t>(g.nslot, (c->lds_budget[l] - used) / tile_b);
       }
-      if (queue)  // tiles in what the queues leave, the rest from the node quads
-        a.lds_tiles = (int)std::min<size_t>(g.nslot, (c->lds_budget_queue - g.nslot * acc_b) / tile_b);
+      if (queue) a.lds_tiles = 0;  // the compacting variant reads f from the node quads
       HIP_TRY(launch_collide_f32(a, g.nslot, queue && n_pass == 1, c->stream), "collide (fp32)");
     }
   }
@@ -213,25 +212,28 @@ qgbe_status run_collide(qgbe_ctx* c, int n_samples, bool learned, double* A, dou
 
 void fill_stats(qgbe_ctx* c, const double* obs, const double* mass2_host, qgbe_stats* st) {
   std::memset(st, 0, sizeof *st);
+  double mass_term = 0.0;
   for (int s = 0; s < kSpecies; ++s) {
-    st->N[s] = obs[s * 5];
-    st->E[s] = obs[s * 5 + 1];
+    st->N[s] = obs[s * kObsPer];
+    st->E[s] = obs[s * kObsPer + 1];
     st->N_total += st->N[s];
     st->E_total += st->E[s];
-    for (int k = 0; k < 3; ++k) st->P[k] += obs[s * 5 + 2 + k];
+    for (int k = 0; k < 3; ++k) st->P[k] += obs[s * kObsPer + 2 + k];
+    mass_term += obs[s * kObsPer + 5];
     double m = 0.0;
     for (int x = 0; x < c->G.cells; ++x) m += mass2_host[s * c->G.cells + x];
     st->mass2_avg[s] = m / c->G.cells;
   }
-  st->min_f = obs[kSpecies * 5];
-  st->max_fermion_f = obs[kSpecies * 5 + 1];
+  st->E_total_mod = st->E_total - 0.25 * mass_term;
+  st->min_f = obs[kSpecies * kObsPer];
+  st->max_fermion_f = obs[kSpecies * kObsPer + 1];
   if (st->min_f < 0.0) st->flags |= QGBE_FLAG_NEGATIVE_F;
   if (st->max_fermion_f > 1.0) st->flags |= QGBE_FLAG_PAULI;
-  if (obs[kSpecies * 5 + 2] > 0.0) st->flags |= QGBE_FLAG_NONFINITE;
+  if (obs[kSpecies * kObsPer + 2] > 0.0) st->flags |= QGBE_FLAG_NONFINITE;
   st->step = c->step;
 }
 
-qgbe_status read_stats(qgbe_ctx* c, qgbe_stats* st) {
+qgbe_status read_stats(qgbe_ctx* c, qgbe_stats* st, bool energy = false) {
   HIP_TRY(launch_observables(c->G, c->d_f, c->d_mass2, c->d_obs_scratch, c->d_obs, c->stream), "observables");
   double obs[observables_len];
   unsigned long long accepted = 0;
@@ -243,8 +245,13 @@ qgbe_status read_stats(qgbe_ctx* c, qgbe_stats* st) {
   HIP_TRY(hipMemcpyAsync(obs, c->d_obs, sizeof obs, hipMemcpyDeviceToHost, c->stream), "copy observables");
   HIP_TRY(hipMemcpyAsync(m2.data(), c->d_mass2, m2.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream),
           "copy masses");
+  double budget[2] = {0.0, 0.0};
+  if (energy)
+    HIP_TRY(hipMemcpyAsync(budget, c->d_energy, sizeof budget, hipMemcpyDeviceToHost, c->stream), "copy energy budget");
   HIP_TRY(hipStreamSynchronize(c->stream), "synchronise");
   fill_stats(c, obs, m2.data(), st);
+  st->E_source = budget[0];
+  st->E_collide = budget[1];
   st->n_accepted = (double)accepted;
   // sum S_i^2 estimates sum (E S_i)^2 + sum Var S_i; remove the variance part
   const double signal = mc[1] - mc[0];
@@ -333,6 +340,7 @@ qgbe_status qgbe_init_grid(const qgbe_grid_desc* desc, qgbe_ctx** out) {
   ALLOC(c->d_lag, (size_t)kSpecies * c->G.cells, "lagged masses");
   ALLOC(c->d_obs_scratch, observables_scratch(c->G), "observables scratch");
   ALLOC(c->d_obs, (size_t)observables_len, "observables");
+  ALLOC(c->d_energy, 2, "energy budget");
   ALLOC(c->d_count, 1, "accepted counter");
   ALLOC(c->d_mc, 2, "error accumulators");
   ALLOC(c->d_chan_var, std::max(1, c->nch), "channel variances");
@@ -386,6 +394,7 @@ void qgbe_destroy(qgbe_ctx* c) {
   (void)hipFree(c->d_mass2);
   (void)hipFree(c->d_lag);
   (void)hipFree(c->d_obs_scratch);
+  (void)hipFree(c->d_energy);
   (void)hipFree(c->d_obs);
   (void)hipFree(c->d_count);
   (void)hipFree(c->d_mc);
@@ -539,6 +548,10 @@ qgbe_status qgbe_step(qgbe_ctx* c, double dt_fm, int32_t n_samples, int32_t samp
     s = run_collide(c, n_samples, sampler == QGBE_SAMPLER_LEARNED, c->d_A, nullptr, nullptr);
     if (s) return s;
     HIP_TRY(hipEventRecord(c->ev[1], c->stream), "event");
+    if (per_step)  // before the update: f_k, its masses, the step before's masses
+      HIP_TRY(launch_energy_budget(c->G, c->d_f, c->d_A, c->d_mass2, c->has_lag ? c->d_lag : nullptr, dt_fm,
+                                   c->d_obs_scratch, c->d_energy, c->stream),
+              "energy budget");
     HIP_TRY(launch_update(c->G, c->d_f, c->d_A, c->d_mass2, dt_fm, c->d.drift, c->d_f_next, c->d_f32, c->stream),
             "update");
     std::swap(c->d_f, c->d_f_next);
@@ -549,7 +562,7 @@ qgbe_status qgbe_step(qgbe_ctx* c, double dt_fm, int32_t n_samples, int32_t samp
     HIP_TRY(hipEventRecord(c->ev[3], c->stream), "event");
     c->step += 1;
     if (per_step) {
-      s = read_stats(c, &per_step[k]);
+      s = read_stats(c, &per_step[k], true);
       if (s) return s;
       float ms = 0.0f;
       (void)hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);

@@ -696,43 +696,56 @@ __device__ __forceinline__ void deposit_slot(int k, int slot_lo, int slot_hi, in
     deposit<double, double>(out + off, widen(st), (double)v, ox, oy);
 }
 
+// Workgroups are dispatched to the 8 XCDs in turn (workgroup b to XCD b mod
+// 8), and each XCD has its own L2.  The logical index hands each XCD a
+// contiguous range of (cell, channel, chunk) work, so the workgroups that
+// read a cell's f quads and flush into its output rows share one L2.
+__device__ __forceinline__ int xcd_local_block(int b, int n) {
+  constexpr int kXcd = 8;
+  const int q = n / kXcd, r = n % kXcd, x = b % kXcd;
+  return x * q + min(x, r) + b / kXcd;
+}
+
 // Workgroup size: 12 waves, 3 per SIMD (the register budget is then 168
 // VGPRs; the learned variant spills a few to scratch and still runs faster
 // than with 8 waves).
 constexpr int f32_threads(bool learned) { return learned ? 768 : 768; }
-// The compacting variant (below) keeps a sample queue per wave in LDS (40 B
-// per entry) next to the accumulators and, where they fit, the f tiles.
+// The compacting variant (below) keeps a sample queue per wave in LDS (52 B
+// per entry) next to the accumulators and reads f from the global node quads.
 constexpr int kQueueWaves = 12;
 constexpr int kQueueLen = 128;  // ring entries per wave (>= 63 pending + 64 new)
 constexpr int f32_block(bool learned, bool queue) { return queue ? kQueueWaves * 64 : f32_threads(learned); }
 
-// kQueue (uniform sampler, every deposit slot in LDS; f tiles in LDS with
-// kAllLds, else from the global node quads): each wave first runs the sample
-// geometry and |M|^2 for 64 samples, appends the accepted ones (the three
-// 23-bit uniforms of p2, p3 in FP64, the value without the bracket in FP32)
-// to its ring in LDS, and evaluates f, bracket and deposits 64 queued samples
-// at a time, so that long path runs on full wavefronts.  Same arithmetic per
-// sample as the direct loop.
+// kQueue (uniform sampler, every deposit slot in LDS, f from the global node
+// quads): each wave first runs the sample geometry for 64 samples, appends
+// the accepted ones (the three 23-bit uniforms of p2, p3 in FP64, s, t, u and
+// the prefactor in FP32) to its ring in LDS, and evaluates |M|^2, f, bracket
+// and deposits 64 queued samples at a time, so that long path runs on full
+// wavefronts.  The deposits of one such batch are issued while the geometry
+// of the next 64 samples runs, a third before, between and after it, so the
+// LDS works off the atomics behind VALU work.  Same arithmetic per sample as
+// the direct loop.
 template <bool kSym, bool kScale, bool kAllLds, bool kLearned, bool kQueue>
 __global__ __launch_bounds__(f32_block(kLearned, kQueue)) void collide_f32_kernel(CollideArgs A) {
-  static_assert(!kQueue || (kSym && !kLearned), "the queue serves the symmetric uniform sampler");
-  // kAllLds: every f tile in LDS (and every accumulator; the queue variant
-  // always keeps its accumulators in LDS)
-  constexpr bool kTilesLds = kAllLds;
-  constexpr bool kAccLds = kAllLds || kQueue;
+  static_assert(!kQueue || (kSym && kAllLds && !kLearned), "the queue serves the uniform sampler, slots in LDS");
+  // kAllLds: every f tile and accumulator in LDS (the queue variant: every
+  // accumulator; f from the quads)
+  constexpr bool kTilesLds = kAllLds && !kQueue;
+  constexpr bool kAccLds = kAllLds;
   extern __shared__ double lds[];
   __shared__ float mix_rows[kLearned ? f32_threads(true) / kWave : 1][kLearned ? kMixRow : 1];
   __shared__ uint32_t q_v[kQueue ? kQueueWaves : 1][3][kQueue ? kQueueLen : 1];  // 23-bit uniforms of p2
   __shared__ double q_p3[kQueue ? kQueueWaves : 1][3][kQueue ? kQueueLen : 1];
-  __shared__ float q_w[kQueue ? kQueueWaves : 1][kQueue ? kQueueLen : 1];       // value without bracket
+  __shared__ float q_f[kQueue ? kQueueWaves : 1][4][kQueue ? kQueueLen : 1];    // s, t, u, prefactor
   __shared__ double mc_wg[2];  // this workgroup's item variances and squared item sums
   const Grid& G = A.G;
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
   const int nw = blockDim.x / kWave;
-  const int chunk = blockIdx.x % A.n_chunks;
-  const int gi = (blockIdx.x / A.n_chunks) % A.n_group;
-  const int cell = blockIdx.x / (A.n_chunks * A.n_group);
+  const int lb = xcd_local_block(blockIdx.x, gridDim.x);
+  const int chunk = lb % A.n_chunks;
+  const int gi = (lb / A.n_chunks) % A.n_group;
+  const int cell = lb / (A.n_chunks * A.n_group);
   const int ci = A.group[gi];
   const Channel ch = A.chans[ci];
   const int nslot = ch.nslot;
@@ -778,9 +791,14 @@ __global__ __launch_bounds__(f32_block(kLearned, kQueue)) void collide_f32_kerne
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
-    // One sample from its five uniforms: FP64 geometry (the decision), FP32
-    // integrand, direct sum and deposits.
-    // integrand and deposits of an accepted sample (wnb = value without bracket)
+    // Queue mode: the deposits of the last evaluated batch, issued while the
+    // next samples' geometry runs (lanes without a sample in a partial batch
+    // deposit zeros).
+    Stencil<float> pd2{}, pd3{}, pd4{};
+    float pdv = 0.0f;
+    bool pending = false;
+    // Integrand, direct sum and deposits of an accepted sample (wnb = value
+    // without the bracket).
     auto finish = [&](const Geo& g, float wnb) {
       ++n_ok;
       const Stencil<float> s2 = make_stencil<float>(g.p2, G);
@@ -798,9 +816,13 @@ __global__ __launch_bounds__(f32_block(kLearned, kQueue)) void collide_f32_kerne
       dsq = fma((double)v, (double)v, dsq);
       if (kScale) ssum += (double)(fabsf(wnb) * (gain + loss));
       if (kSym) {
-        deposit_slot<kAccLds>(k2, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off2, s2, v, nodes, G.ox, G.oy);
-        deposit_slot<kAccLds>(k3, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off3, s3, -v, nodes, G.ox, G.oy);
-        deposit_slot<kAccLds>(k4, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off4, s4, -v, nodes, G.ox, G.oy);
+        if (kQueue) {
+          pd2 = s2; pd3 = s3; pd4 = s4; pdv = v;
+        } else {
+          deposit_slot<kAccLds>(k2, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off2, s2, v, nodes, G.ox, G.oy);
+          deposit_slot<kAccLds>(k3, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off3, s3, -v, nodes, G.ox, G.oy);
+          deposit_slot<kAccLds>(k4, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off4, s4, -v, nodes, G.ox, G.oy);
+        }
         if (kScale && A.direct) {
           const float vs = fabsf(wnb) * (gain + loss);
           deposit<double, double>(A.scale + ((size_t)ch.sp[1] * G.cells + cell) * nodes, widen(s2), (double)vs, G.ox, G.oy);
@@ -825,17 +847,21 @@ __global__ __launch_bounds__(f32_block(kLearned, kQueue)) void collide_f32_kerne
           g.p3[a] = q_p3[wid][a][slot];
           g.p4[a] = (it.p1[a] + g.p2[a]) - g.p3[a];
         }
-        finish(g, q_w[wid][slot]);
+        const float m = matrix_element<float>(ch.row, q_f[wid][0][slot], q_f[wid][1][slot], q_f[wid][2][slot],
+                                              (float)it.mu);
+        finish(g, m * q_f[wid][3][slot]);
       };
       unsigned head = 0, tail = 0;  // ring positions (wave-uniform)
       for (int base = 0; base < A.n_samples; base += kWave) {
         const int s = base + lane;
         uint32_t x0 = (uint32_t)s, x1 = (uint32_t)p1_lin, x2 = (uint32_t)cell, x3 = ((uint32_t)ch.code << 8);
         philox4x32_10(x0, x1, x2, x3, A.key0, A.key1);
+        if (pending) deposit_slot<true>(k2, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off2, pd2, pdv, nodes, G.ox, G.oy);
         double u[5];
         five_uniforms(x0, x1, x2, x3, u);
         Geo g;
         const bool ok = s < A.n_samples && geometry(it, G, u, g);
+        if (pending) deposit_slot<true>(k3, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off3, pd3, -pdv, nodes, G.ox, G.oy);
         const unsigned long long mask = __ballot(ok);
         if (ok) {
           const unsigned slot = (tail + (unsigned)__popcll(mask & ((1ull << lane) - 1ull))) & (kQueueLen - 1);
@@ -843,21 +869,37 @@ __global__ __launch_bounds__(f32_block(kLearned, kQueue)) void collide_f32_kerne
           q_v[wid][1][slot] = x1 >> 9;
           q_v[wid][2][slot] = x2 >> 9;
           for (int a = 0; a < 3; ++a) q_p3[wid][a][slot] = g.p3[a];
-          q_w[wid][slot] = weight_no_bracket<float>(it, g, ch.row);
+          q_f[wid][0][slot] = (float)g.s;
+          q_f[wid][1][slot] = (float)g.t;
+          q_f[wid][2][slot] = (float)g.u;
+          q_f[wid][3][slot] = prefactor<float>(it, g);
         }
+        if (pending) deposit_slot<true>(k4, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off4, pd4, -pdv, nodes, G.ox, G.oy);
+        pending = false;
         tail += (unsigned)__popcll(mask);
         if (tail - head >= (unsigned)kWave) {
           wave_lds_sync();
+          pdv = 0.0f;
           finish_queued((head + lane) & (kQueueLen - 1));
+          pending = true;
           head += kWave;
           wave_lds_sync();
         }
       }
-      if (tail != head) {  // the last, partial batch
+      auto flush = [&]() {
+        deposit_slot<true>(k2, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off2, pd2, pdv, nodes, G.ox, G.oy);
+        deposit_slot<true>(k3, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off3, pd3, -pdv, nodes, G.ox, G.oy);
+        deposit_slot<true>(k4, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off4, pd4, -pdv, nodes, G.ox, G.oy);
+      };
+      if (pending) flush();  // the last full batch
+      if (tail != head) {    // the last, partial batch
         wave_lds_sync();
+        pdv = 0.0f;
         if ((unsigned)lane < tail - head) finish_queued((head + lane) & (kQueueLen - 1));
+        flush();
         wave_lds_sync();
       }
+      pending = false;
     } else
     for (int s = lane; s < A.n_samples; s += kWave) {
       uint32_t x0 = (uint32_t)s, x1 = (uint32_t)p1_lin, x2 = (uint32_t)cell, x3 = ((uint32_t)ch.code << 8);
@@ -995,10 +1037,7 @@ void launch_f32_variant(const CollideArgs& a, bool all_lds, bool queue, dim3 gri
                         hipStream_t st) {
   if constexpr (kSym && !kLearned) {
     if (queue) {
-      if (all_lds)
-        hipLaunchKernelGGL((collide_f32_kernel<true, kScale, true, false, true>), grid, block, lds, st, a);
-      else
-        hipLaunchKernelGGL((collide_f32_kernel<true, kScale, false, false, true>), grid, block, lds, st, a);
+      hipLaunchKernelGGL((collide_f32_kernel<true, kScale, true, false, true>), grid, block, lds, st, a);
       return;
     }
   }
@@ -1046,7 +1085,7 @@ hipError_t set_collide_lds_limit(size_t lds_max, size_t* budget_plain, size_t* b
   // runtime's default; after a refusal the budget is the limit in force.
   // Groups: 0 uniform sampler, 1 learned sampler, 2 the compacting variant.
   struct Fn { const void* fn; int group; };
-  const Fn fns[20] = {
+  const Fn fns[18] = {
       {(const void*)collide_f32_kernel<true, true, true, false, false>, 0},
       {(const void*)collide_f32_kernel<true, false, true, false, false>, 0},
       {(const void*)collide_f32_kernel<false, true, true, false, false>, 0},
@@ -1064,9 +1103,7 @@ hipError_t set_collide_lds_limit(size_t lds_max, size_t* budget_plain, size_t* b
       {(const void*)collide_f32_kernel<false, true, false, true, false>, 1},
       {(const void*)collide_f32_kernel<false, false, false, true, false>, 1},
       {(const void*)collide_f32_kernel<true, true, true, false, true>, 2},
-      {(const void*)collide_f32_kernel<true, false, true, false, true>, 2},
-      {(const void*)collide_f32_kernel<true, true, false, false, true>, 2},
-      {(const void*)collide_f32_kernel<true, false, false, false, true>, 2}};
+      {(const void*)collide_f32_kernel<true, false, true, false, true>, 2}};
   size_t budget[3] = {lds_max, lds_max, lds_max};
   for (const Fn& f : fns) {
     hipFuncAttributes attr;

@@ -70,6 +70,7 @@ struct qgbe_ctx {
   bool masses_valid = false;       // d_mass2 holds the masses of the current f
   double* d_A = nullptr;
   double* d_obs_scratch = nullptr;
+  double* d_energy = nullptr;  // [E_source, E_collide] of the last step
   double* d_obs = nullptr;
   unsigned long long* d_count = nullptr;
   double* d_mc = nullptr;          // [2] MC error accumulators of the last collision term

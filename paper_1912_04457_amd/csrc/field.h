@@ -10,8 +10,10 @@ struct Mass7 {
 };
 
 // Observables layout in `out` (length observables_len): per species
-// [N, E, Px, Py, Pz] (7 x 5), then min f, max fermion f, non-finite count.
-constexpr int observables_len = kSpecies * 5 + 3;
+// [N, E, Px, Py, Pz, M] (7 x 6) with M = sum N dV m^2 f / E, then min f,
+// max fermion f, non-finite count.
+constexpr int kObsPer = 6;
+constexpr int observables_len = kSpecies * kObsPer + 3;
 
 hipError_t launch_masses(const Grid& G, const double* f, const double* lag, double* mass2, hipStream_t st);
 hipError_t launch_const_masses(const Grid& G, const Mass7& m, double* mass2, hipStream_t st);
@@ -20,6 +22,10 @@ hipError_t launch_update(const Grid& G, const double* f, const double* A, const 
 size_t observables_scratch(const Grid& G);
 hipError_t launch_observables(const Grid& G, const double* f, const double* mass2, double* scratch,
                               double* out, hipStream_t st);
+// out[0] = E_source, out[1] = E_collide of a step (mass2_prev NULL: no
+// source term); scratch as for launch_observables.
+hipError_t launch_energy_budget(const Grid& G, const double* f, const double* A, const double* mass2,
+                                const double* mass2_prev, double dt, double* scratch, double* out, hipStream_t st);
 hipError_t launch_to_f32(const double* src, float* dst, size_t n, hipStream_t st);
 // Node quads of the FP32 field: q[i] = (f[i], f[i+1], f[i+oy], f[i+oy+1])
 // within each (species, cell) block, so a trilinear read takes two 16-byte

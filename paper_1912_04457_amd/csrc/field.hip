@@ -150,9 +150,10 @@ __global__ __launch_bounds__(kBlock) void update_kernel(Grid G, const double* __
   }
 }
 
-// Observables: per species N, E, P (3), then min f and max fermion f, and a
-// non-finite counter.  Stage 1: per-block partials; stage 2: one block.
-constexpr int kObs = kSpecies * 5;
+// Observables: per species N, E, P (3) and M = sum m^2 f / E (the mass term
+// of the modified tensor), then min f and max fermion f, and a non-finite
+// counter.  Stage 1: per-block partials; stage 2: one block.
+constexpr int kObs = kSpecies * kObsPer;
 
 __global__ __launch_bounds__(kBlock) void observables_partial(Grid G, const double* __restrict__ f,
                                                               const double* __restrict__ mass2,
@@ -161,16 +162,18 @@ __global__ __launch_bounds__(kBlock) void observables_partial(Grid G, const doub
   const size_t per = (size_t)G.cells * G.nodes;
   double minf = 1e300, maxq = -1e300, bad = 0.0;
   for (int sp = 0; sp < kSpecies; ++sp) {
-    double N = 0.0, E = 0.0, P0 = 0.0, P1 = 0.0, P2 = 0.0;
+    double N = 0.0, E = 0.0, P0 = 0.0, P1 = 0.0, P2 = 0.0, M = 0.0;
     const bool evolve = (G.species_mask >> sp) & 1u;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < per; i += (size_t)gridDim.x * blockDim.x) {
       const int cell = (int)(i / G.nodes), node = (int)(i % G.nodes);
       const double fv = f[(size_t)sp * per + i];
       double p[3];
       node_p(G, node, p);
-      const double En = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2] + mass2[sp * G.cells + cell]);
+      const double m2 = mass2[sp * G.cells + cell];
+      const double En = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2] + m2);
       N += fv;
       E += En * fv;
+      if (En > 0.0) M += m2 * fv / En;
       P0 += p[0] * fv;
       P1 += p[1] * fv;
       P2 += p[2] * fv;
@@ -180,10 +183,10 @@ __global__ __launch_bounds__(kBlock) void observables_partial(Grid G, const doub
         if (sp != kGluon) maxq = fmax(maxq, fv);
       }
     }
-    const double vals[5] = {N, E, P0, P1, P2};
-    for (int k = 0; k < 5; ++k) {
+    const double vals[kObsPer] = {N, E, P0, P1, P2, M};
+    for (int k = 0; k < kObsPer; ++k) {
       const double t = block_sum(vals[k], sh);
-      if (threadIdx.x == 0) partial[(size_t)blockIdx.x * (kObs + 3) + sp * 5 + k] = t;
+      if (threadIdx.x == 0) partial[(size_t)blockIdx.x * (kObs + 3) + sp * kObsPer + k] = t;
     }
   }
   // min / max over the block
@@ -233,8 +236,58 @@ __global__ __launch_bounds__(kBlock) void observables_final(Grid G, const double
       }
     } else {
       const double t = block_sum(v, sh);
-      if (threadIdx.x == 0) out[k] = (k < kObs) ? t * degeneracy(k / 5) * meas : t;
+      if (threadIdx.x == 0) out[k] = (k < kObs) ? t * degeneracy(k / kObsPer) * meas : t;
     }
+  }
+}
+
+// Energy bookkeeping of a step, per-block partials [source, collide]:
+// source  = sum N f (E(m^2) - E(m_prev^2)), the difference taken as
+//           (m^2 - m_prev^2) / (E + E_prev) so it keeps its relative accuracy;
+// collide = sum over evolved species of E(m^2) A.
+__global__ __launch_bounds__(kBlock) void energy_partial(Grid G, const double* __restrict__ f,
+                                                         const double* __restrict__ A,
+                                                         const double* __restrict__ mass2,
+                                                         const double* __restrict__ mass2_prev, double* partial) {
+  __shared__ double sh[kBlock / 64];
+  const size_t per = (size_t)G.cells * G.nodes;
+  double src = 0.0, col = 0.0;
+  for (int sp = 0; sp < kSpecies; ++sp) {
+    const bool evolve = (G.species_mask >> sp) & 1u;
+    double s_sp = 0.0;
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < per; i += (size_t)gridDim.x * blockDim.x) {
+      const int cell = (int)(i / G.nodes), node = (int)(i % G.nodes);
+      double p[3];
+      node_p(G, node, p);
+      const double pp = p[0] * p[0] + p[1] * p[1] + p[2] * p[2];
+      const double m2 = mass2[sp * G.cells + cell];
+      const double E = sqrt(pp + m2);
+      if (mass2_prev) {
+        const double m2p = mass2_prev[sp * G.cells + cell];
+        const double den = E + sqrt(pp + m2p);
+        if (den > 0.0) s_sp += f[(size_t)sp * per + i] * (m2 - m2p) / den;
+      }
+      if (evolve) col += E * A[(size_t)sp * per + i];
+    }
+    src += degeneracy(sp) * s_sp;
+  }
+  const double t0 = block_sum(src, sh);
+  const double t1 = block_sum(col, sh);
+  if (threadIdx.x == 0) {
+    partial[2 * (size_t)blockIdx.x] = t0;
+    partial[2 * (size_t)blockIdx.x + 1] = t1;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void energy_final(Grid G, const double* partial, int nblocks, double dt,
+                                                       double* out) {
+  __shared__ double sh[kBlock / 64];
+  const double meas = G.dx[0] * G.dx[1] * G.dx[2] * G.dp[0] * G.dp[1] * G.dp[2] / (8.0 * kPi * kPi * kPi);
+  for (int k = 0; k < 2; ++k) {
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) v += partial[2 * (size_t)b + k];
+    const double t = block_sum(v, sh);
+    if (threadIdx.x == 0) out[k] = k == 0 ? t * meas : t * meas * dt / kHbarC;
   }
 }
 
@@ -299,6 +352,14 @@ hipError_t launch_observables(const Grid& G, const double* f, const double* mass
   const int nb = observables_blocks(G);
   hipLaunchKernelGGL(observables_partial, dim3(nb), dim3(kBlock), 0, st, G, f, mass2, scratch);
   hipLaunchKernelGGL(observables_final, dim3(1), dim3(kBlock), 0, st, G, scratch, nb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_budget(const Grid& G, const double* f, const double* A, const double* mass2,
+                                const double* mass2_prev, double dt, double* scratch, double* out, hipStream_t st) {
+  const int nb = observables_blocks(G);
+  hipLaunchKernelGGL(energy_partial, dim3(nb), dim3(kBlock), 0, st, G, f, A, mass2, mass2_prev, scratch);
+  hipLaunchKernelGGL(energy_final, dim3(1), dim3(kBlock), 0, st, G, scratch, nb, dt, out);
   return hipGetLastError();
 }
 

@@ -59,7 +59,8 @@ class Stats(C.Structure):
                 ("E", C.c_double * 7), ("P", C.c_double * 3), ("mass2_avg", C.c_double * 7),
                 ("min_f", C.c_double), ("max_fermion_f", C.c_double), ("n_evals", C.c_double),
                 ("t_collide_ms", C.c_double), ("t_step_ms", C.c_double), ("flags", C.c_uint32),
-                ("step", C.c_uint32), ("n_accepted", C.c_double), ("mc_err_est", C.c_double)]
+                ("step", C.c_uint32), ("n_accepted", C.c_double), ("mc_err_est", C.c_double),
+                ("E_source", C.c_double), ("E_collide", C.c_double), ("E_total_mod", C.c_double)]
 
     def as_dict(self) -> dict:
         out = {}

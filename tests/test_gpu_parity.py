@@ -163,8 +163,35 @@ def test_step_parity_fp64(O):
         assert a["N_total"] == pytest.approx(b["N_total"], rel=1e-13)
         assert a["E_total"] == pytest.approx(b["E_total"], rel=1e-12)
         assert np.allclose(a["mass2_avg"], b["mass2"].mean(axis=1), rtol=1e-12)
+        # energy bookkeeping (Eq. current conservation; modified tensor of Sec. IV)
+        assert abs(a["E_source"] - b["E_source"]) <= 1e-12 * b["E_total"]
+        assert abs(a["E_collide"] - b["E_collide"]) <= 1e-12 * b["E_total"]
+        assert a["E_total_mod"] == pytest.approx(b["E_total_mod"], rel=1e-12)
+    assert stats[0]["E_source"] == 0.0 and stats[1]["E_source"] != 0.0
     N0 = O.observables(g, f0, O.masses(g, f0))["N_total"]
     assert abs(stats[-1]["N_total"] - N0) <= 1e-13 * N0
+
+
+def test_energy_source_accounts_for_kinetic_energy_change():
+    """The energy test of Sec. IV with dynamic masses: in a homogeneous pure
+    gluon system the kinetic energy changes by the mass source term plus the
+    collision term's grid residue, step by step (FP32 integrand; the
+    bookkeeping itself is FP64)."""
+    _case("energy bookkeeping fp32")
+    wl = W.Workload("g_1cell_10cube", (1, 1, 1), (10, 10, 10), (3.0, 3.0, 3.0), (2.0, 2.0, 2.0),
+                    1 << 6, 128, "f32", 4, 0.01)
+    P = W.node_momenta(wl.n_p, wl.p_half)
+    f0 = np.zeros((7, 1, wl.nodes))
+    f0[6, 0] = 0.5 * (np.linalg.norm(P, axis=1) < 1.5)
+    with qgbe.Solver(**_grid_kw(wl), precision=qgbe.FP32, seed=SEED) as s:
+        s.set_f(f0)
+        stats = s.step(wl.dt_fm, wl.n_samples, n_steps=4)
+    for k in range(1, 4):
+        change = stats[k]["E_total"] - stats[k - 1]["E_total"]
+        parts = stats[k]["E_source"] + stats[k]["E_collide"]
+        assert abs(change - parts) <= 1e-12 * stats[k]["E_total"], k
+        assert abs(stats[k]["E_collide"]) < 0.05 * abs(stats[k]["E_source"])
+    assert all(st["E_total_mod"] < st["E_total"] for st in stats)
 
 
 def test_step_parity_central_fp32(O):

@@ -95,6 +95,8 @@ def lib():
                                                p, p, p, i32]
         _lib.ref_item_sums.restype = i32
         _lib.ref_item_sums.argtypes = [p, p, p, u64, u32, i32, i32, C.c_int64, p, p, p, i32]
+        _lib.ref_item_sums_est.restype = i32
+        _lib.ref_item_sums_est.argtypes = [p, p, p, u64, u32, i32, i32, i32, C.c_int64, p, p, p, i32]
         _lib.ref_collision_points.restype = i32
         _lib.ref_collision_points.argtypes = [p, p, p, C.c_int64, p, p, i32, i32, p, i32]
         _lib.ref_drift.restype = i32
@@ -240,7 +242,7 @@ def collision(grid: Grid, f, mass2, seed: int, step: int, n_samples: int, *, est
     items = np.zeros((grid.cells, nch, grid.nodes)) if want_items else None
     e = _make_eq(eq)
     g = grid.c()
-    est = {"cm": 0, "root": 1}[estimator]
+    est = {"cm": 0, "root": 1, "root_k3": 2}[estimator]
     r = lib().ref_collision(C.byref(g), _ptr(f), _ptr(mass2), seed, step, n_samples, est,
                             int(symmetric), flags, None if e is None else C.byref(e),
                             _ptr(A), _ptr(S), _ptr(items), threads)
@@ -282,7 +284,8 @@ def collision_learned(grid: Grid, f, mass2, seed: int, step: int, n_samples: int
 
 
 def item_sums(grid: Grid, f, mass2, seed: int, step: int, n_samples: int, items, *,
-              symmetric: bool = True, want_scale: bool = False, threads: int = 0):
+              symmetric: bool = True, want_scale: bool = False, threads: int = 0,
+              estimator: str = "cm"):
     """Sum of the sample values of each selected (cell, channel, node) item;
     with want_scale also the sum of the samples' gain+loss magnitudes."""
     f = _field(grid, f)
@@ -291,8 +294,9 @@ def item_sums(grid: Grid, f, mass2, seed: int, step: int, n_samples: int, items,
     out = np.zeros(len(items))
     scale = np.zeros(len(items)) if want_scale else None
     g = grid.c()
-    if lib().ref_item_sums(C.byref(g), _ptr(f), _ptr(mass2), seed, step, n_samples, int(symmetric),
-                           len(items), _ptr(items), _ptr(out), _ptr(scale), threads) < 0:
+    est = {"cm": 0, "root": 1, "root_k3": 2}[estimator]
+    if lib().ref_item_sums_est(C.byref(g), _ptr(f), _ptr(mass2), seed, step, n_samples, est, int(symmetric),
+                               len(items), _ptr(items), _ptr(out), _ptr(scale), threads) < 0:
         raise ValueError("oracle rejected the arguments")
     return (out, scale) if want_scale else out
 

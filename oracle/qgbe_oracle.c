@@ -486,6 +486,71 @@ static int eval_root(const ref_grid* g, const ref_channel* ch, const double* f,
 }
 
 /* ------------------------------------------------------------------ */
+/* The alternative elimination (the paper's second choice): k4 and     */
+/* k3x, k3y sampled, k2 = k3 + k4 - k1, and k3z from energy            */
+/* conservation E3 - E2 = E1 - E4 =: D.  With Q = k4 - k1 and           */
+/* a = k3x^2 + k3y^2 + m3^2, squaring |k3 + Q|^2 + m2^2 = (E3 - D)^2    */
+/* gives C + 2 Qz k3z = -2 D E3, C = 2 (k3x Qx + k3y Qy) + Q^2 + m2^2  */
+/* - m3^2 - D^2, and squaring again the quadratic                      */
+/* (Qz^2 - D^2) z^2 + C Qz z + (C^2/4 - D^2 a) = 0.  A root counts when */
+/* the unsquared equation holds (C + 2 Qz z and D of opposite signs,   */
+/* E2 = E3 - D > 0).  Its coefficient Qz^2 - D^2 has no fixed sign,    */
+/* unlike the W^2 - Qz^2 = s + Q_perp^2 > 0 of the paper's choice.      */
+/* ------------------------------------------------------------------ */
+static int eval_root_k3(const ref_grid* g, const ref_channel* ch, const double* f,
+                        const double* mass2, int64_t cell, const double p1[3], int64_t p1_lin,
+                        const double p4[3], double p3x, double p3y, int flags,
+                        const ref_equilibrium* eq, ref_point pts[2]) {
+  const int64_t nc = n_cells(g);
+  double m2[4];
+  for (int i = 0; i < 4; ++i)
+    m2[i] = (flags & REF_MASSLESS) ? 0.0 : mass2_of(mass2, nc, ch->sp[i], cell);
+  const double mg2 = mass2_of(mass2, nc, GLUON, cell);
+  const double E1 = sqrt(norm2(p1) + m2[0]), E4 = sqrt(norm2(p4) + m2[3]);
+  const double D = E1 - E4;
+  const double Q[3] = {p4[0] - p1[0], p4[1] - p1[1], p4[2] - p1[2]};
+  const double a = p3x * p3x + p3y * p3y + m2[2];
+  const double C = 2.0 * (p3x * Q[0] + p3y * Q[1]) + norm2(Q) + m2[1] - m2[2] - D * D;
+  const double den = Q[2] * Q[2] - D * D;
+  const double H = C * C + 4.0 * a * den;
+  int nv = 0;
+  if (!(H >= 0.0) || den == 0.0 || D == 0.0) return 0;
+  const double sq = fabs(D) * sqrt(H);
+  for (int r = 0; r < 2; ++r) {
+    const double z = (-C * Q[2] + (r == 0 ? 1.0 : -1.0) * sq) / (2.0 * den);
+    if (!((C + 2.0 * Q[2] * z) * D < 0.0)) continue;
+    const double E3 = sqrt(a + z * z);
+    if (!(E3 - D > 0.0)) continue;
+    const double p3[3] = {p3x, p3y, z};
+    const double p2[3] = {p3[0] + Q[0], p3[1] + Q[1], p3[2] + Q[2]};
+    const double E2 = sqrt(norm2(p2) + m2[1]);
+    ref_point* o = &pts[nv];
+    memset(o, 0, sizeof *o);
+    const double k1[4] = {E1, p1[0], p1[1], p1[2]};
+    const double k2[4] = {E2, p2[0], p2[1], p2[2]};
+    const double k3[4] = {E3, p3[0], p3[1], p3[2]};
+    const double k4[4] = {E4, p4[0], p4[1], p4[2]};
+    for (int q = 0; q < 4; ++q) { o->k[0][q] = k1[q]; o->k[1][q] = k2[q]; o->k[2][q] = k3[q]; o->k[3][q] = k4[q]; }
+    if (!(flags & REF_NO_BOXCUT) && (!inside_box(g, p2) || !inside_box(g, p3))) continue;
+    double P[4], d13[4], d14[4];
+    for (int q = 0; q < 4; ++q) { P[q] = k1[q] + k2[q]; d13[q] = k1[q] - k3[q]; d14[q] = k1[q] - k4[q]; }
+    o->s = mink2(P);
+    o->t = mink2(d13);
+    o->u = mink2(d14);
+    o->msq = ref_msq(ch->row, o->s, o->t, o->u, mg2, g->alpha_s);
+    bracket(g, ch, f, cell, p1_lin, (const double(*)[4])o->k, flags, eq, o);
+    /* d(E1 + E2 - E3 - E4)/dk3z with k2 = k3 + Q */
+    const double J = fabs(p2[2] / E2 - z / E3);
+    const double norm = 1.0 / (pow(2.0 * PI, 5) * 16.0 * E1 * E2 * E3 * E4 * J);
+    o->g = o->msq * o->B * norm;
+    o->gscale = fabs(o->msq) * o->GL * norm;
+    o->valid = 1;
+    ++nv;
+  }
+  return nv;
+}
+
+/* ------------------------------------------------------------------ */
 /* Work items.  One (cell, channel, p1) item draws its N samples from   */
 /* Philox4x32-10 with key (seed_lo, seed_hi + step) and counter         */
 /* (s, p1_lin, cell, code<<8 | block).                                  */
@@ -546,7 +611,10 @@ static void run_item_uniform(const ref_grid* g, const ref_channel* ch, const dou
       const double p3x = -g->p_half[0] + 2.0 * g->p_half[0] * u[3];
       const double p3y = -g->p_half[1] + 2.0 * g->p_half[1] * u[4];
       ref_point pts[2];
-      const int nv = eval_root(g, ch, f, mass2, cell, p1, p1_lin, p2, p3x, p3y, flags, eq, pts);
+      /* the box-uniform momentum is k2 for the paper's choice, k4 for the alternative */
+      const int nv = (estimator == REF_EST_ROOT)
+                         ? eval_root(g, ch, f, mass2, cell, p1, p1_lin, p2, p3x, p3y, flags, eq, pts)
+                         : eval_root_k3(g, ch, f, mass2, cell, p1, p1_lin, p2, p3x, p3y, flags, eq, pts);
       for (int r = 0; r < nv; ++r) {
         const double v = ch->w * V5 * pts[r].g / N, vs = ch->w * V5 * pts[r].gscale / N;
         const double vd = ch->sigma * V5 * pts[r].g / N, vsd = ch->sigma * V5 * pts[r].gscale / N;
@@ -721,7 +789,16 @@ static int32_t run_all(const run_args* ra, item_kind kind, double* A_out, double
 int32_t ref_item_sums(const ref_grid* g, const double* f, const double* mass2, uint64_t seed,
                       uint32_t step, int32_t n_samples, int32_t symmetric, int64_t n_sel,
                       const int64_t* items, double* out, double* out_scale, int32_t n_threads) {
+  return ref_item_sums_est(g, f, mass2, seed, step, n_samples, REF_EST_CM, symmetric, n_sel, items, out,
+                           out_scale, n_threads);
+}
+
+int32_t ref_item_sums_est(const ref_grid* g, const double* f, const double* mass2, uint64_t seed,
+                          uint32_t step, int32_t n_samples, int32_t estimator, int32_t symmetric,
+                          int64_t n_sel, const int64_t* items, double* out, double* out_scale,
+                          int32_t n_threads) {
   if (check_grid(g) || n_samples <= 0) return -1;
+  if (estimator < REF_EST_CM || estimator > REF_EST_ROOT_K3) return -1;
   ref_channel chans[128];
   const int nch = ref_channels(g, chans, 128);
   if (nch < 0) return -1;
@@ -741,7 +818,7 @@ int32_t ref_item_sums(const ref_grid* g, const double* f, const double* mass2, u
 #endif
   for (int64_t i = 0; i < n_sel; ++i) {
     accum acc = {NULL, NULL};
-    run_item_uniform(g, &chans[items[3 * i + 1]], f, mass2, seed, step, n_samples, REF_EST_CM,
+    run_item_uniform(g, &chans[items[3 * i + 1]], f, mass2, seed, step, n_samples, estimator,
                      symmetric, 0, NULL, items[3 * i], items[3 * i + 2], &acc, &out[i],
                      out_scale ? &out_scale[i] : NULL);
   }
@@ -754,6 +831,7 @@ int32_t ref_collision(const ref_grid* g, const double* f, const double* mass2,
                       const ref_equilibrium* eq, double* A_out, double* S_out,
                       double* item_sum, int32_t n_threads) {
   if ((flags & REF_ANALYTIC_F) && !eq) return -1;
+  if (estimator < REF_EST_CM || estimator > REF_EST_ROOT_K3) return -1;
   run_args ra = {g, f, mass2, seed, step, n_samples, estimator, symmetric, flags, eq,
                  0, NULL, NULL, NULL, 0, NULL};
   return run_all(&ra, ITEM_UNIFORM, A_out, S_out, item_sum, n_threads);

@@ -73,7 +73,17 @@ enum {
   REF_ANALYTIC_F = 8      /* f from Eq. fg / Eq. fq at the exact momenta   */
 };
 
-enum { REF_EST_CM = 0, REF_EST_ROOT = 1 };
+/* estimators of the uniform sampler.  In channel order k1 + k2 <-> k3 + k4,
+   k1 the observed momentum (the paper's p):
+     REF_EST_CM       CM-angle parameterisation (p2 in the box, two angles)
+     REF_EST_ROOT     the paper's choice (Eq. work out delta E): k2 in the box,
+                      k3x, k3y sampled, k3z from the roots, k4 eliminated
+                      (the paper eliminates its k2, on the other side of p)
+     REF_EST_ROOT_K3  the paper's alternative (Sec. III A, stability test):
+                      k4 in the box, k3x, k3y sampled, k3z from the roots, k2
+                      eliminated (the paper eliminates its k3, the partner of
+                      p); the roots then depend on E1 - E4, which changes sign */
+enum { REF_EST_CM = 0, REF_EST_ROOT = 1, REF_EST_ROOT_K3 = 2 };
 
 /* Philox4x32-10 block (Salmon et al., SC'11) */
 void ref_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -97,8 +107,9 @@ int32_t ref_eval_cm(const ref_grid* g, const ref_channel* ch, const double* f,
                     ref_point* out);
 
 /* the Monte Carlo collision term, uniform sampler.
- *   estimator  REF_EST_CM (CM-angle sampler) or REF_EST_ROOT (the paper's
- *              own k2-elimination with the k1z roots, Eq. work-out-delta-E)
+ *   estimator  REF_EST_CM (CM-angle sampler), REF_EST_ROOT (the paper's
+ *              own elimination with the k1z roots, Eq. work-out-delta-E) or
+ *              REF_EST_ROOT_K3 (the alternative elimination)
  *   symmetric  1 = symmetric sampling, 0 = direct estimator
  *   A_out      [7][cells][nodes], overwritten
  *   S_out      same shape or NULL: sum of |deposit| of the gain+loss scale
@@ -117,6 +128,11 @@ int32_t ref_collision(const ref_grid* g, const double* f, const double* mass2,
 int32_t ref_item_sums(const ref_grid* g, const double* f, const double* mass2, uint64_t seed,
                       uint32_t step, int32_t n_samples, int32_t symmetric, int64_t n_sel,
                       const int64_t* items, double* out, double* out_scale, int32_t n_threads);
+/* the same for any estimator of the uniform sampler */
+int32_t ref_item_sums_est(const ref_grid* g, const double* f, const double* mass2, uint64_t seed,
+                          uint32_t step, int32_t n_samples, int32_t estimator, int32_t symmetric,
+                          int64_t n_sel, const int64_t* items, double* out, double* out_scale,
+                          int32_t n_threads);
 
 /* the collision term with a mixture-of-logistic-normals proposal.
  *   K          mixture components

@@ -9,6 +9,11 @@ What the paper and the mathematics fix, independent of the oracle's own code:
 * two independent parameterisations of the same 5-D integral -- the CM-angle
   sampler and the paper's own elimination of one momentum with the k1z roots
   (Eq. work out delta E, Eq. delta replace) -- agree in expectation;
+* the paper's alternative elimination (of the momentum paired with the
+  observed one) is a third parameterisation of the same integral and agrees in
+  expectation too; in the stability test of Sec. IV A (random f, one step of
+  the direct estimator) the particle number it gives spreads more over
+  independent evaluations than the paper's choice;
 * the Monte Carlo mean equals a deterministic Gauss-Legendre quadrature of the
   same integrand (brute force on a 4^3 grid);
 * the symmetric and direct estimators agree in expectation up to the O(dp^2)
@@ -94,6 +99,39 @@ def test_two_parameterisations_agree_quarks(O):
     z = _zstats(cm, rt)
     assert np.mean(z ** 2) < 1.7, np.mean(z ** 2)
     assert np.abs(z).max() < 5.5
+
+
+def test_alternative_elimination_agrees_gluons(O):
+    g = O.Grid(n_p=(6, 6, 6), p_half=(2.0, 2.0, 2.0), species_mask=1 << G)
+    f = W.smooth_f(1, g.n_p, g.p_half, species_mask=1 << G)
+    m = O.masses(g, f)
+    R = 24
+    cm = np.array([O.collision(g, f, m, 1000 + r, 0, 2000, want_scale=False)[0][G, 0] for r in range(R)])
+    alt = np.array([O.collision(g, f, m, 3000 + r, 0, 4000, estimator="root_k3", want_scale=False)[0][G, 0]
+                    for r in range(R)])
+    z = _zstats(cm, alt)
+    assert np.mean(z ** 2) < 1.6, np.mean(z ** 2)
+    assert np.abs(z).max() < 5.0
+
+
+def test_alternative_elimination_spreads_more(O):
+    """Sec. IV A at 20^3 nodes: f uniform in [0, 1], one step of dt = 0.01 fm
+    with 100 samples per node and the direct estimator; the spread of the
+    gluon number over 32 independent evaluations."""
+    g = O.Grid(n_p=(20, 20, 20), x_half=(3.0, 3.0, 3.0), p_half=(2.0, 2.0, 2.0), species_mask=1 << G)
+    rng = np.random.Generator(np.random.PCG64(7))
+    f = np.zeros((7, 1, g.nodes))
+    f[G, 0] = rng.uniform(0.0, 1.0, g.nodes)
+    m = O.masses(g, f)
+    spread = {}
+    for est in ("cm", "root", "root_k3"):
+        N = []
+        for r in range(32):
+            A = O.collision(g, f, m, 100 + r, 0, 100, estimator=est, symmetric=False, want_scale=False)[0]
+            N.append(O.observables(g, f + 0.01 * A / (O.DEGENERACY[:, None, None] * O.HBARC), m)["N_total"])
+        spread[est] = np.std(N, ddof=1)
+    assert spread["root_k3"] > 1.2 * spread["root"], spread
+    assert spread["cm"] < spread["root"], spread
 
 
 def _gl_points(n, P):

@@ -44,6 +44,15 @@ SLOTS_ACCEPTED = SLOTS_REJECTED + 16 + 27 + 123 + 17 + 66
 # y = mu + sigma z), the mixture density 210 (8 components x 5 dimensions x
 # 3 ops, 8 exponentials, 5 log-Jacobian terms, one log).
 SLOTS_LEARNED_EXTRA = 120 + 110 + 210
+# The root parameterisation (FP64, per sample): Philox 120, uniforms 20, the
+# sampled momenta and a 3, the quadratic's coefficients and square root 31,
+# each of its two roots 15 (z, E3, the sign test); per accepted root: the
+# eliminated momentum and its energy 10, J 9, box 6, s, t, u 24, |M|^2 27, the
+# value 8, stencils and interpolations 123, bracket 17, and with symmetric
+# sampling the deposits 66.
+SLOTS_ROOTS_SAMPLE = 120 + 20 + 8 + 31 + 2 * 15
+SLOTS_ROOTS_ACCEPTED = 10 + 9 + 6 + 24 + 27 + 8 + 123 + 17
+SLOTS_DEPOSITS = 66
 # MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = one full-rate lane op per slot
 ALU_PEAK_SLOTS = 256 * 64 * 2.4e9
 # LDS: 128 B/clk/CU -> 32 four-byte lane accesses per clock per CU
@@ -259,7 +268,9 @@ def cpu_baseline(wl, f, n_samples, budget_s):
         fs = np.ascontiguousarray(f[:, cells_done:cells_done + k])
         t0 = time.perf_counter()
         m = O.masses(g, fs)
-        O.collision(g, fs, m, W.PHILOX_SEED, 0, n_samples, want_scale=False, threads=threads)
+        O.collision(g, fs, m, W.PHILOX_SEED, 0, n_samples, want_scale=False, threads=threads,
+                    estimator={"roots": "root", "roots_alt": "root_k3"}.get(wl.sampler, "cm"),
+                    symmetric=wl.symmetric)
         dt = time.perf_counter() - t0
         total_t += dt
         total_evals += k * nch * wl.nodes * n_samples
@@ -295,13 +306,14 @@ def main():
     drift = qgbe.DRIFT_UPWIND if wl.drift == "upwind" else qgbe.DRIFT_CENTRAL
     solver = qgbe.Solver(n_x=wl.n_x, n_p=wl.n_p, x_half=wl.x_half, p_half=wl.p_half,
                          species_mask=wl.species_mask, alpha_s=wl.alpha_s, precision=prec,
-                         drift=drift, seed=W.PHILOX_SEED, device=0)
+                         drift=drift, seed=W.PHILOX_SEED, device=0, symmetric=int(wl.symmetric))
     solver.set_f(f0)
-    sampler = qgbe.SAMPLER_UNIFORM
+    sampler = {"uniform": qgbe.SAMPLER_UNIFORM, "learned": qgbe.SAMPLER_LEARNED, "roots": qgbe.SAMPLER_ROOTS,
+               "roots_alt": qgbe.SAMPLER_ROOTS_ALT}[wl.sampler]
+    roots = sampler in (qgbe.SAMPLER_ROOTS, qgbe.SAMPLER_ROOTS_ALT)
     prep = None
-    if wl.sampler == "learned":
+    if sampler == qgbe.SAMPLER_LEARNED:
         prep = train_proposal(solver, wl, a.train_epochs)
-        sampler = qgbe.SAMPLER_LEARNED
     if a.warmup:
         solver.step(wl.dt_fm, N, n_steps=a.warmup, sampler=sampler)
     torch.cuda.synchronize()
@@ -315,7 +327,12 @@ def main():
     accepted = sum(s["n_accepted"] for s in stats)
     t_coll = np.array([s["t_collide_ms"] for s in stats]) * 1e-3
     value = evals / elapsed
-    slots = SLOTS_ACCEPTED * accepted + SLOTS_REJECTED * (evals - accepted)
+    if roots:   # accepted counts the roots that passed
+        slots = SLOTS_ROOTS_SAMPLE * evals + (SLOTS_ROOTS_ACCEPTED + SLOTS_DEPOSITS * wl.symmetric) * accepted
+    else:
+        slots = SLOTS_ACCEPTED * accepted + SLOTS_REJECTED * (evals - accepted)
+        if not wl.symmetric:
+            slots -= SLOTS_DEPOSITS * accepted
     if sampler == qgbe.SAMPLER_LEARNED:
         slots += SLOTS_LEARNED_EXTRA * evals
     achieved = slots / t_coll.sum()
@@ -323,9 +340,10 @@ def main():
     roof = dict(bound="alu", achieved=achieved, peak=ALU_PEAK_SLOTS, unit="lane-op slots/s",
                 frac=achieved / ALU_PEAK_SLOTS,
                 traffic=traffic,
-                kernel="collide_f32_kernel" if prec == qgbe.FP32 else "collide_f64_kernel",
+                kernel="collide_roots_kernel" if roots else
+                ("collide_f32_kernel" if prec == qgbe.FP32 else "collide_f64_kernel"),
                 kernel_ms_avg=float(t_coll.mean() * 1e3),
-                lds_frac=(LDS_PER_ACCEPTED * accepted / t_coll.sum()) / LDS_PEAK,
+                lds_frac=None if roots or prec == qgbe.FP64 else (LDS_PER_ACCEPTED * accepted / t_coll.sum()) / LDS_PEAK,
                 hbm_frac=None if traffic is None else traffic / float(t_coll.mean()) / HBM_PEAK)
     N0 = stats[0]["N_total"]
     out = {
@@ -335,7 +353,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "cells": wl.cells, "momentum_nodes": wl.nodes,
                    "species_mask": wl.species_mask, "channels": solver.n_channels,
-                   "samples_per_point": N, "sampler": wl.sampler, "symmetric": True,
+                   "samples_per_point": N, "sampler": wl.sampler, "symmetric": wl.symmetric,
                    "precision": "fp32 integrand, fp64 geometry + accumulation" if prec == qgbe.FP32
                    else "fp64", "drift": wl.drift, "dt_fm": wl.dt_fm},
         "roofline": roof,

@@ -59,7 +59,12 @@ typedef enum {
 } qgbe_status;
 
 enum { QGBE_FP64 = 0, QGBE_FP32 = 1 };                 /* integrand precision   */
-enum { QGBE_SAMPLER_UNIFORM = 0, QGBE_SAMPLER_LEARNED = 1 };
+enum {
+  QGBE_SAMPLER_UNIFORM = 0,   /* CM-angle parameterisation, uniform draws       */
+  QGBE_SAMPLER_LEARNED = 1,   /* the proposal table's mixture, weight 1/q       */
+  QGBE_SAMPLER_ROOTS = 2,     /* the paper's root parameterisation (FP64)       */
+  QGBE_SAMPLER_ROOTS_ALT = 3  /* its alternative elimination (FP64)             */
+};
 enum { QGBE_DRIFT_UPWIND = 0, QGBE_DRIFT_CENTRAL = 1 };
 enum { QGBE_MASS_DYNAMIC = 0, QGBE_MASS_CONSTANT = 1 };
 
@@ -203,6 +208,14 @@ qgbe_status qgbe_restore(qgbe_ctx* ctx, const void* buf, size_t bytes);
  * draws from the proposal table (qgbe_set_proposal_table, or the network's
  * table re-evaluated on the current masses after qgbe_proposal_build_table),
  * with weight 1/q, except on channels set back to the uniform sampler.
+ * QGBE_SAMPLER_ROOTS is the paper's own parameterisation (Eq. work out delta
+ * E, Eq. delta replace, Eq. ca): in channel order k1 + k2 <-> k3 + k4 with k1
+ * observed, k2 uniform in the box, k3x and k3y uniform, k4 eliminated by
+ * momentum conservation and k3z at each of the two roots of energy
+ * conservation, weighted 1/|J|.  QGBE_SAMPLER_ROOTS_ALT eliminates k2 instead
+ * (k4 uniform in the box), the alternative whose spread the paper compares
+ * (Sec. IV A).  Both run in FP64 (f from the FP64 field) whatever the
+ * context's precision, with Philox block 2 of the same counters.
  * Symmetric sampling (Eq. small c relation) adds each sample's value at the
  * observed node and at the trilinear stencils of the other three momenta with
  * signs (+,+,-,-), so sum_{Y,q} A = 0 per cell exactly.

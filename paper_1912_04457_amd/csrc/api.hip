@@ -39,7 +39,8 @@ qgbe_status compute_masses(qgbe_ctx* c) {
     for (int s = 0; s < kSpecies; ++s) m.v[s] = c->d.const_mass2[s];
     HIP_TRY(launch_const_masses(c->G, m, c->d_mass2, c->stream), "constant masses");
   } else {
-    HIP_TRY(launch_masses(c->G, c->d_f, c->has_lag ? c->d_lag : nullptr, c->d_mass2, c->stream), "masses");
+    HIP_TRY(launch_masses(c->G, c->d_f, c->has_lag ? c->d_lag : nullptr, c->d_mass_part, c->d_mass2, c->stream),
+            "masses");
   }
   c->masses_valid = true;
   return QGBE_OK;
@@ -152,7 +153,8 @@ void plan_groups(qgbe_ctx* c) {
 }
 
 // Enqueue the collision kernels accumulating into A (zeroed by the caller).
-qgbe_status run_collide(qgbe_ctx* c, int n_samples, bool learned, double* A, double* scale, double* items) {
+qgbe_status run_collide(qgbe_ctx* c, int n_samples, int sampler, double* A, double* scale, double* items) {
+  const bool learned = sampler == QGBE_SAMPLER_LEARNED;
   HIP_TRY(launch_zero_u64(c->d_count, c->stream), "zero counter");
   HIP_TRY(launch_fill(c->d_mc, 0.0, 2, c->stream), "zero error accumulators");
   HIP_TRY(launch_fill(c->d_chan_var, 0.0, std::max(1, c->nch), c->stream), "zero channel variances");
@@ -162,6 +164,13 @@ qgbe_status run_collide(qgbe_ctx* c, int n_samples, bool learned, double* A, dou
   a.slot_lo = 0;
   a.slot_hi = 3;
   a.direct = 1;
+  if (sampler == QGBE_SAMPLER_ROOTS || sampler == QGBE_SAMPLER_ROOTS_ALT) {
+    a.learned = 0;
+    a.group = c->d_all;
+    a.n_group = c->nch;
+    HIP_TRY(launch_collide_roots(a, sampler == QGBE_SAMPLER_ROOTS_ALT, c->stream), "collide (roots)");
+    return QGBE_OK;
+  }
   const bool f64_path = c->d.precision == QGBE_FP64;
   if (f64_path) {
     a.group = c->d_all;
@@ -341,6 +350,7 @@ qgbe_status qgbe_init_grid(const qgbe_grid_desc* desc, qgbe_ctx** out) {
   ALLOC(c->d_obs_scratch, observables_scratch(c->G), "observables scratch");
   ALLOC(c->d_obs, (size_t)observables_len, "observables");
   ALLOC(c->d_energy, 2, "energy budget");
+  ALLOC(c->d_mass_part, mass_scratch(c->G), "mass partial sums");
   ALLOC(c->d_count, 1, "accepted counter");
   ALLOC(c->d_mc, 2, "error accumulators");
   ALLOC(c->d_chan_var, std::max(1, c->nch), "channel variances");
@@ -395,6 +405,7 @@ void qgbe_destroy(qgbe_ctx* c) {
   (void)hipFree(c->d_lag);
   (void)hipFree(c->d_obs_scratch);
   (void)hipFree(c->d_energy);
+  (void)hipFree(c->d_mass_part);
   (void)hipFree(c->d_obs);
   (void)hipFree(c->d_count);
   (void)hipFree(c->d_mc);
@@ -470,7 +481,7 @@ qgbe_status qgbe_collision_term_ex(qgbe_ctx* c, int32_t n_samples, int32_t sampl
                                    int32_t on_device, const qgbe_collide_extras* ex, qgbe_stats* st) {
   if (!c || !A_out) return fail(QGBE_EINVAL, "NULL argument");
   if (n_samples < 1) return fail(QGBE_EINVAL, "n_samples must be >= 1");
-  if (sampler != QGBE_SAMPLER_UNIFORM && sampler != QGBE_SAMPLER_LEARNED) return fail(QGBE_EINVAL, "bad sampler");
+  if (sampler < QGBE_SAMPLER_UNIFORM || sampler > QGBE_SAMPLER_ROOTS_ALT) return fail(QGBE_EINVAL, "bad sampler");
   if (sampler == QGBE_SAMPLER_LEARNED && !c->K) return fail(QGBE_ESTATE, "no proposal table installed");
   HIP_TRY(hipSetDevice(c->d.device), "hipSetDevice");
   const size_t n = field_len(c);
@@ -495,7 +506,7 @@ qgbe_status qgbe_collision_term_ex(qgbe_ctx* c, int32_t n_samples, int32_t sampl
     if (e == hipSuccess) e = hipEventRecord(c->ev[0], c->stream);
     if (e != hipSuccess) s = hip_fail(e, "zero outputs");
   }
-  if (!s) s = run_collide(c, n_samples, sampler == QGBE_SAMPLER_LEARNED, A, scale, items);
+  if (!s) s = run_collide(c, n_samples, sampler, A, scale, items);
   if (!s) {
     hipError_t e = hipEventRecord(c->ev[1], c->stream);
     if (e == hipSuccess && !on_device)
@@ -533,7 +544,7 @@ qgbe_status qgbe_step(qgbe_ctx* c, double dt_fm, int32_t n_samples, int32_t samp
   if (!c) return fail(QGBE_EINVAL, "NULL context");
   if (!(dt_fm > 0.0) || !std::isfinite(dt_fm)) return fail(QGBE_EINVAL, "dt must be > 0");
   if (n_samples < 1 || n_steps < 0) return fail(QGBE_EINVAL, "n_samples >= 1 and n_steps >= 0 required");
-  if (sampler != QGBE_SAMPLER_UNIFORM && sampler != QGBE_SAMPLER_LEARNED) return fail(QGBE_EINVAL, "bad sampler");
+  if (sampler < QGBE_SAMPLER_UNIFORM || sampler > QGBE_SAMPLER_ROOTS_ALT) return fail(QGBE_EINVAL, "bad sampler");
   if (sampler == QGBE_SAMPLER_LEARNED && !c->K) return fail(QGBE_ESTATE, "no proposal table installed");
   HIP_TRY(hipSetDevice(c->d.device), "hipSetDevice");
   const size_t n = field_len(c);
@@ -545,7 +556,7 @@ qgbe_status qgbe_step(qgbe_ctx* c, double dt_fm, int32_t n_samples, int32_t samp
     if (s) return s;
     HIP_TRY(launch_fill(c->d_A, 0.0, n, c->stream), "zero A");
     HIP_TRY(hipEventRecord(c->ev[0], c->stream), "event");
-    s = run_collide(c, n_samples, sampler == QGBE_SAMPLER_LEARNED, c->d_A, nullptr, nullptr);
+    s = run_collide(c, n_samples, sampler, c->d_A, nullptr, nullptr);
     if (s) return s;
     HIP_TRY(hipEventRecord(c->ev[1], c->stream), "event");
     if (per_step)  // before the update: f_k, its masses, the step before's masses

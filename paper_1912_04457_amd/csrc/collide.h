@@ -41,6 +41,8 @@ struct CollideArgs {
 };
 
 hipError_t launch_collide_f64(const CollideArgs& a, hipStream_t stream);
+// The paper's root parameterisation (FP64; alt: the alternative elimination).
+hipError_t launch_collide_roots(const CollideArgs& a, bool alt, hipStream_t stream);
 // queue: use the compacting variant if the launch qualifies (uniform sampler,
 // symmetric, every tile and accumulator in LDS within the queue budget).
 hipError_t launch_collide_f32(const CollideArgs& a, int nslot, bool queue, hipStream_t stream);

@@ -539,6 +539,37 @@ __device__ __forceinline__ double item_variance(double s, double sq, int n) {
 
 }  // namespace
 
+// Per-workgroup totals of the accepted count and the two error sums: the
+// waves add into LDS and one thread adds the workgroup's totals into global
+// memory at the end (one global atomic per workgroup instead of per item).
+struct BlockTotals {
+  unsigned long long* ok;
+  double* mc;  // [2]
+  __device__ void init() {
+    if (threadIdx.x == 0) {
+      *ok = 0ull;
+      mc[0] = 0.0;
+      mc[1] = 0.0;
+    }
+    __syncthreads();
+  }
+  __device__ void add(int n_ok, double var, double sq) {
+    __hip_atomic_fetch_add(ok, (unsigned long long)n_ok, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(&mc[0], var, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(&mc[1], sq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+  __device__ void flush(unsigned long long* g_ok, double* g_mc) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      if (g_ok) atomicAdd(g_ok, *ok);
+      if (g_mc) {
+        atomicAdd(&g_mc[0], mc[0]);
+        atomicAdd(&g_mc[1], mc[1]);
+      }
+    }
+  }
+};
+
 // ---------------------------------------------------------------------------
 // FP64 kernel: f read from the FP64 field in global memory, deposits as FP64
 // atomics into the output.  This is the reference-precision path.
@@ -546,6 +577,10 @@ __device__ __forceinline__ double item_variance(double s, double sq, int n) {
 template <bool kLearned>
 __global__ __launch_bounds__(256) void collide_f64_kernel(CollideArgs A) {
   const Grid& G = A.G;
+  __shared__ unsigned long long blk_ok;
+  __shared__ double blk_mc[2];
+  BlockTotals blk{&blk_ok, blk_mc};
+  blk.init();
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int nwaves = gridDim.x * blockDim.x / kWave;
@@ -630,18 +665,196 @@ __global__ __launch_bounds__(256) void collide_f64_kernel(CollideArgs A) {
     if (A.mc_acc) dsq = wave_sum(dsq);
     const int ok_total = wave_count(n_ok);
     if (lane == 0) {
-      if (A.n_accepted) atomicAdd(A.n_accepted, (unsigned long long)ok_total);
-      if (A.mc_acc) {
-        const double var = item_variance(dsum, dsq, A.n_samples);
-        atomicAdd(&A.mc_acc[0], var);
-        atomicAdd(&A.mc_acc[1], dsum * dsum);
-        if (A.chan_var) atomicAdd(&A.chan_var[ci], var);
-      }
+      blk.add(ok_total, A.mc_acc ? item_variance(dsum, dsq, A.n_samples) : 0.0, dsum * dsum);
+      if (A.mc_acc && A.chan_var) atomicAdd(&A.chan_var[ci], item_variance(dsum, dsq, A.n_samples));
       atomicAdd(Ac[0] + p1_lin, dsum);
       if (A.scale) atomicAdd(Sc[0] + p1_lin, ssum);
       if (A.items) A.items[((size_t)cell * A.n_channels + ci) * G.nodes + p1_lin] = dsum;
     }
   }
+  blk.flush(A.n_accepted, A.mc_acc);
+}
+
+// ---------------------------------------------------------------------------
+// The paper's own parameterisation (Eq. work out delta E, Eq. delta replace):
+// momentum conservation eliminates one momentum, energy conservation fixes
+// one z component at the two roots of a quadratic, and each root carries
+// 1/|J|.  In channel order k1 + k2 <-> k3 + k4 with k1 observed (the
+// paper's p):
+//   kAlt = false, the paper's choice: k2 uniform in the box, k3x and k3y
+//     uniform, k4 = k1 + k2 - k3; E1 + E2 = E3 + E4 has the roots
+//     z = (c Qz +- W sqrt(c^2 - 4 a (W^2 - Qz^2))) / (2 (W^2 - Qz^2)) with
+//     W = E1 + E2 > 0, Q = k1 + k2, a = k3x^2 + k3y^2 + m3^2,
+//     c = W^2 + a - (Qx - k3x)^2 - (Qy - k3y)^2 - m4^2 - Qz^2; a root holds
+//     when c + 2 Qz z > 0 and E3 < W;
+//   kAlt = true, the alternative the paper tests (Sec. IV A): k4 uniform in
+//     the box, k3x and k3y uniform, k2 = k3 + k4 - k1; E3 - E2 = D = E1 - E4
+//     gives z = (-C Qz +- |D| sqrt(C^2 + 4 a (Qz^2 - D^2))) / (2 (Qz^2 - D^2))
+//     with Q = k4 - k1, C = 2 (k3x Qx + k3y Qy) + Q^2 + m2^2 - m3^2 - D^2; a
+//     root holds when (C + 2 Qz z) D < 0 and E3 > D.  Its leading
+//     coefficient has no fixed sign: the instability the paper reports.
+// The value of a root is w V5 / N |M|^2 B / ((2 pi)^5 16 E1 E2 E3 E4 |J|),
+// V5 = (2 P)^3 (2 Px) (2 Py), J the z derivative of the energy sum.  FP64
+// throughout (f from the FP64 field, FP64 atomics): the reference method.
+// ---------------------------------------------------------------------------
+constexpr double kRootNorm = 1.0 / (32.0 * kPi * kPi * kPi * kPi * kPi * 16.0);
+
+template <bool kAlt>
+__global__ __launch_bounds__(256) void collide_roots_kernel(CollideArgs A) {
+  const Grid& G = A.G;
+  __shared__ unsigned long long blk_ok;
+  __shared__ double blk_mc[2];
+  BlockTotals blk{&blk_ok, blk_mc};
+  blk.init();
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int nwaves = gridDim.x * blockDim.x / kWave;
+  const long long n_items = (long long)G.cells * A.n_group * G.nodes;
+  for (long long w = wave; w < n_items; w += nwaves) {
+    const int p1_lin = (int)(w % G.nodes);
+    const int gi = (int)((w / G.nodes) % A.n_group);
+    const int cell = (int)(w / ((long long)G.nodes * A.n_group));
+    const int ci = A.group[gi];
+    const Channel ch = A.chans[ci];
+    Item it;
+    load_item(it, A, ch, cell, p1_lin);
+    if (!(it.E1 > 0.0)) {  // massless p = 0 node: zero measure
+      if (lane == 0 && A.items) A.items[((size_t)cell * A.n_channels + ci) * G.nodes + p1_lin] = 0.0;
+      continue;
+    }
+    const double* fc[4];
+    double* Ac[4];
+    double* Sc[4];
+    for (int p = 0; p < 4; ++p) {
+      fc[p] = A.f64 + ((size_t)ch.sp[p] * G.cells + cell) * G.nodes;
+      Ac[p] = A.A + ((size_t)ch.sp[p] * G.cells + cell) * G.nodes;
+      Sc[p] = A.scale ? A.scale + ((size_t)ch.sp[p] * G.cells + cell) * G.nodes : nullptr;
+    }
+    const bool g1 = is_gluon(ch.sp[0]), g2 = is_gluon(ch.sp[1]);
+    const bool g3 = is_gluon(ch.sp[2]), g4 = is_gluon(ch.sp[3]);
+    const double F1 = g1 ? 1.0 + it.f1 : 1.0 - it.f1;
+    const double V5 = G.Vp * (2.0 * G.ph[0]) * (2.0 * G.ph[1]);
+    const double coef = (A.symmetric ? ch.w : ch.sigma) * V5 / (double)A.n_samples * G.g4 * kRootNorm / it.E1;
+    double dsum = 0.0, ssum = 0.0, dsq = 0.0;
+    int n_ok = 0;
+    for (int s = lane; s < A.n_samples; s += kWave) {
+      uint32_t x0 = (uint32_t)s, x1 = (uint32_t)p1_lin, x2 = (uint32_t)cell, x3 = ((uint32_t)ch.code << 8) | 2u;
+      philox4x32_10(x0, x1, x2, x3, A.key0, A.key1);
+      double u[5];
+      five_uniforms(x0, x1, x2, x3, u);
+      double q[3];  // k2 (the paper's choice) or k4 (the alternative), uniform in the box
+      for (int a = 0; a < 3; ++a) q[a] = fma(2.0 * G.ph[a], u[a], -G.ph[a]);
+      const double k3x = fma(2.0 * G.ph[0], u[3], -G.ph[0]);
+      const double k3y = fma(2.0 * G.ph[1], u[4], -G.ph[1]);
+      const double a3 = k3x * k3x + k3y * k3y + it.m3sq;
+      const double Eq = sqrt64(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + (kAlt ? it.m4sq : it.m2sq));
+      double Q[3], lin, half, den, W = 0.0, D = 0.0, C = 0.0;
+      bool any;
+      if (!kAlt) {
+        W = it.E1 + Eq;
+        for (int a = 0; a < 3; ++a) Q[a] = it.p1[a] + q[a];
+        const double b = (Q[0] - k3x) * (Q[0] - k3x) + (Q[1] - k3y) * (Q[1] - k3y) + it.m4sq;
+        C = W * W + a3 - b - Q[2] * Q[2];
+        den = W * W - Q[2] * Q[2];
+        const double H = C * C - 4.0 * a3 * den;
+        any = H >= 0.0 && den > 0.0;
+        lin = C * Q[2];
+        half = any ? W * sqrt64(H) : 0.0;
+      } else {
+        D = it.E1 - Eq;
+        for (int a = 0; a < 3; ++a) Q[a] = q[a] - it.p1[a];
+        C = 2.0 * (k3x * Q[0] + k3y * Q[1]) + (Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2]) + it.m2sq - it.m3sq - D * D;
+        den = Q[2] * Q[2] - D * D;
+        const double H = C * C + 4.0 * a3 * den;
+        any = H >= 0.0 && den != 0.0 && D != 0.0;
+        lin = -C * Q[2];
+        half = any ? fabs(D) * sqrt64(H) : 0.0;
+      }
+      double vsample = 0.0;
+      const double inv_2den = any ? rcp64(2.0 * den) : 0.0;
+#pragma unroll 1
+      for (int r = 0; r < 2 && any; ++r) {
+        const double z = (lin + (r == 0 ? half : -half)) * inv_2den;
+        const double E3 = sqrt64(a3 + z * z);
+        double p2[3], p3[3] = {k3x, k3y, z}, p4[3], E2, E4, J;
+        if (!kAlt) {
+          if (!(C + 2.0 * Q[2] * z > 0.0) || !(E3 < W)) continue;
+          for (int a = 0; a < 3; ++a) {
+            p2[a] = q[a];
+            p4[a] = Q[a] - p3[a];
+          }
+          E2 = Eq;
+          E4 = sqrt64(p4[0] * p4[0] + p4[1] * p4[1] + p4[2] * p4[2] + it.m4sq);
+          J = fabs(z * rcp64(E3) - p4[2] * rcp64(E4));
+        } else {
+          if (!((C + 2.0 * Q[2] * z) * D < 0.0) || !(E3 - D > 0.0)) continue;
+          for (int a = 0; a < 3; ++a) {
+            p4[a] = q[a];
+            p2[a] = p3[a] + Q[a];
+          }
+          E4 = Eq;
+          E2 = sqrt64(p2[0] * p2[0] + p2[1] * p2[1] + p2[2] * p2[2] + it.m2sq);
+          J = fabs(p2[2] * rcp64(E2) - z * rcp64(E3));
+        }
+        bool inside = true;
+        for (int a = 0; a < 3; ++a) {
+          inside = inside && fabs(p3[a]) <= G.ph[a];
+          inside = inside && (kAlt ? fabs(p2[a]) <= G.ph[a] : fabs(p4[a]) <= G.ph[a]);
+        }
+        if (!inside) continue;
+        ++n_ok;
+        double Pq[3], d13[3], d14[3];
+        for (int a = 0; a < 3; ++a) {
+          Pq[a] = it.p1[a] + p2[a];
+          d13[a] = it.p1[a] - p3[a];
+          d14[a] = it.p1[a] - p4[a];
+        }
+        const double E12 = it.E1 + E2, E13 = it.E1 - E3, E14 = it.E1 - E4;
+        const double ms = E12 * E12 - (Pq[0] * Pq[0] + Pq[1] * Pq[1] + Pq[2] * Pq[2]);
+        const double mt = E13 * E13 - (d13[0] * d13[0] + d13[1] * d13[1] + d13[2] * d13[2]);
+        const double mu = E14 * E14 - (d14[0] * d14[0] + d14[1] * d14[1] + d14[2] * d14[2]);
+        const double wnb = coef * matrix_element<double>(ch.row, ms, mt, mu, it.mu) * rcp64(E2 * E3 * E4 * J);
+        const Stencil<double> s2 = make_stencil<double>(p2, G);
+        const Stencil<double> s3 = make_stencil<double>(p3, G);
+        const Stencil<double> s4 = make_stencil<double>(p4, G);
+        const double f2 = interpolate<double>(fc[1], s2, G.ox, G.oy);
+        const double f3 = interpolate<double>(fc[2], s3, G.ox, G.oy);
+        const double f4 = interpolate<double>(fc[3], s4, G.ox, G.oy);
+        const double F2 = g2 ? 1.0 + f2 : 1.0 - f2;
+        const double F3 = g3 ? 1.0 + f3 : 1.0 - f3;
+        const double F4 = g4 ? 1.0 + f4 : 1.0 - f4;
+        const double gain = f3 * f4 * F1 * F2, loss = it.f1 * f2 * F3 * F4;
+        const double v = wnb * (gain - loss);
+        const double vs = fabs(wnb) * (gain + loss);
+        vsample += v;
+        ssum += vs;
+        if (A.symmetric) {
+          deposit<double, double>(Ac[1], s2, v, G.ox, G.oy);
+          deposit<double, double>(Ac[2], s3, -v, G.ox, G.oy);
+          deposit<double, double>(Ac[3], s4, -v, G.ox, G.oy);
+          if (A.scale) {
+            deposit<double, double>(Sc[1], s2, vs, G.ox, G.oy);
+            deposit<double, double>(Sc[2], s3, vs, G.ox, G.oy);
+            deposit<double, double>(Sc[3], s4, vs, G.ox, G.oy);
+          }
+        }
+      }
+      dsum += vsample;
+      dsq = fma(vsample, vsample, dsq);
+    }
+    dsum = wave_sum(dsum);
+    if (A.scale) ssum = wave_sum(ssum);
+    if (A.mc_acc) dsq = wave_sum(dsq);
+    const int ok_total = wave_count(n_ok);
+    if (lane == 0) {
+      blk.add(ok_total, A.mc_acc ? item_variance(dsum, dsq, A.n_samples) : 0.0, dsum * dsum);
+      if (A.mc_acc && A.chan_var) atomicAdd(&A.chan_var[ci], item_variance(dsum, dsq, A.n_samples));
+      atomicAdd(Ac[0] + p1_lin, dsum);
+      if (A.scale) atomicAdd(Sc[0] + p1_lin, ssum);
+      if (A.items) A.items[((size_t)cell * A.n_channels + ci) * G.nodes + p1_lin] = dsum;
+    }
+  }
+  blk.flush(A.n_accepted, A.mc_acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -738,6 +951,7 @@ __global__ __launch_bounds__(f32_block(kLearned, kQueue)) void collide_f32_kerne
   __shared__ double q_p3[kQueue ? kQueueWaves : 1][3][kQueue ? kQueueLen : 1];
   __shared__ float q_f[kQueue ? kQueueWaves : 1][4][kQueue ? kQueueLen : 1];    // s, t, u, prefactor
   __shared__ double mc_wg[2];  // this workgroup's item variances and squared item sums
+  __shared__ unsigned long long ok_wg;  // and its accepted samples
   const Grid& G = A.G;
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
@@ -761,6 +975,7 @@ __global__ __launch_bounds__(f32_block(kLearned, kQueue)) void collide_f32_kerne
   }
   for (int i = threadIdx.x; i < n_acc * nodes; i += blockDim.x) acc[i] = 0.0;
   if (threadIdx.x < 2) mc_wg[threadIdx.x] = 0.0;
+  if (threadIdx.x == 0) ok_wg = 0ull;
   for (int k = 0; k < n_tiles; ++k)
     for (int i = threadIdx.x; i < nodes; i += blockDim.x) tiles[k * nodes + i] = A.f32[goff[k] + i];
   __syncthreads();
@@ -924,7 +1139,7 @@ __global__ __launch_bounds__(f32_block(kLearned, kQueue)) void collide_f32_kerne
     dsq = wave_sum(dsq);
     const int ok_total = wave_count(n_ok);
     if (lane == 0) {
-      if (A.n_accepted) atomicAdd(A.n_accepted, (unsigned long long)ok_total);
+      __hip_atomic_fetch_add(&ok_wg, (unsigned long long)ok_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       __hip_atomic_fetch_add(&mc_wg[0], item_variance(dsum, dsq, A.n_samples), __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_WORKGROUP);
       __hip_atomic_fetch_add(&mc_wg[1], dsum * dsum, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -935,6 +1150,7 @@ __global__ __launch_bounds__(f32_block(kLearned, kQueue)) void collide_f32_kerne
   }
   __syncthreads();
   if (threadIdx.x < 2 && A.mc_acc && A.direct) atomicAdd(&A.mc_acc[threadIdx.x], mc_wg[threadIdx.x]);
+  if (threadIdx.x == 0 && A.n_accepted && A.direct) atomicAdd(A.n_accepted, ok_wg);
   if (threadIdx.x == 0 && A.chan_var && A.direct) atomicAdd(&A.chan_var[ci], mc_wg[0]);  // one channel per workgroup
   if (n_acc > 0) {
     for (int i = threadIdx.x; i < n_acc * nodes; i += blockDim.x) {
@@ -1019,11 +1235,24 @@ hipError_t launch_record(const CollideArgs& a, int n_per_item, long long item_st
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+hipError_t launch_collide_roots(const CollideArgs& a, bool alt, hipStream_t stream) {
+  const long long items = (long long)a.G.cells * a.n_group * a.G.nodes;
+  const int threads = 256;
+  long long blocks = (items * kWave + threads - 1) / threads;
+  if (blocks > 4096) blocks = 4096;  // 16 waves per CU; the rest by the grid-stride loop
+  if (blocks < 1) blocks = 1;
+  if (alt)
+    hipLaunchKernelGGL(collide_roots_kernel<true>, dim3((unsigned)blocks), dim3(threads), 0, stream, a);
+  else
+    hipLaunchKernelGGL(collide_roots_kernel<false>, dim3((unsigned)blocks), dim3(threads), 0, stream, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_collide_f64(const CollideArgs& a, hipStream_t stream) {
   const long long items = (long long)a.G.cells * a.n_group * a.G.nodes;
   const int threads = 256;
   long long blocks = (items * kWave + threads - 1) / threads;
-  if (blocks > 65536) blocks = 65536;
+  if (blocks > 4096) blocks = 4096;  // 16 waves per CU; the rest by the grid-stride loop
   if (blocks < 1) blocks = 1;
   if (a.learned)
     hipLaunchKernelGGL(collide_f64_kernel<true>, dim3((unsigned)blocks), dim3(threads), 0, stream, a);

@@ -71,6 +71,7 @@ struct qgbe_ctx {
   double* d_A = nullptr;
   double* d_obs_scratch = nullptr;
   double* d_energy = nullptr;  // [E_source, E_collide] of the last step
+  double* d_mass_part = nullptr;  // per (cell, chunk, species) partial mass integrals
   double* d_obs = nullptr;
   unsigned long long* d_count = nullptr;
   double* d_mc = nullptr;          // [2] MC error accumulators of the last collision term

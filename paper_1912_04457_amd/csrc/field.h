@@ -15,7 +15,10 @@ struct Mass7 {
 constexpr int kObsPer = 6;
 constexpr int observables_len = kSpecies * kObsPer + 3;
 
-hipError_t launch_masses(const Grid& G, const double* f, const double* lag, double* mass2, hipStream_t st);
+// Thermal masses (Eq. mg, Eq. mq); scratch holds mass_scratch(G) doubles.
+size_t mass_scratch(const Grid& G);
+hipError_t launch_masses(const Grid& G, const double* f, const double* lag, double* scratch, double* mass2,
+                         hipStream_t st);
 hipError_t launch_const_masses(const Grid& G, const Mass7& m, double* mass2, hipStream_t st);
 hipError_t launch_update(const Grid& G, const double* f, const double* A, const double* mass2, double dt,
                          int scheme, double* f_out, float* f32, hipStream_t st);

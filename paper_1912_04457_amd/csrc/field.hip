@@ -32,37 +32,54 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return t;  // valid in thread 0
 }
 
-// One block per cell.  I_Y = sum_p dV/(2pi)^3 f_Y / (2 E_Y), E_Y from the
-// lagged masses (or |p| when there are none; a node at p = 0 then adds 0).
-__global__ __launch_bounds__(kBlock) void mass_kernel(Grid G, const double* __restrict__ f,
-                                                      const double* __restrict__ lag, double* mass2) {
+// I_Y = sum_p dV/(2pi)^3 f_Y / (2 E_Y) per cell, E_Y from the lagged masses
+// (or |p| when there are none; a node at p = 0 then adds 0).  Stage 1: block
+// (chunk, cell) sums kMassChunk nodes of every species; stage 2: one thread
+// per cell adds its chunks in order (deterministic) and applies Eq. mg / mq.
+constexpr int kMassChunk = 2048;
+
+int mass_chunks(const Grid& G) { return (G.nodes + kMassChunk - 1) / kMassChunk; }
+
+__global__ __launch_bounds__(kBlock) void mass_partial(Grid G, const double* __restrict__ f,
+                                                       const double* __restrict__ lag, double* part) {
   __shared__ double sh[kBlock / 64];
-  const int cell = blockIdx.x;
-  const double meas = G.dp[0] * G.dp[1] * G.dp[2] / (8.0 * kPi * kPi * kPi);
-  double I[kSpecies];
+  const int chunk = blockIdx.x, cell = blockIdx.y;
+  const int lo = chunk * kMassChunk, hi = min(G.nodes, lo + kMassChunk);
   for (int sp = 0; sp < kSpecies; ++sp) {
     const double m2 = lag ? lag[sp * G.cells + cell] : 0.0;
     const double* fc = f + ((size_t)sp * G.cells + cell) * G.nodes;
     double acc = 0.0;
-    for (int node = threadIdx.x; node < G.nodes; node += blockDim.x) {
+    for (int node = lo + threadIdx.x; node < hi; node += blockDim.x) {
       double p[3];
       node_p(G, node, p);
       const double E = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2] + m2);
       if (E > 0.0) acc += fc[node] / (2.0 * E);
     }
-    I[sp] = block_sum(acc, sh) * meas;
+    const double t = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[((size_t)cell * gridDim.x + chunk) * kSpecies + sp] = t;
   }
-  if (threadIdx.x == 0) {
-    // SU(3): dA = 8, CA = 3, CF = 4/3; N_g = 16, N_q = 6
-    const double CF = 4.0 / 3.0;
-    double q = 0.0;
-    for (int i = 0; i < 3; ++i) q += 6.0 * CF * (I[i] + I[i + 3]);
-    mass2[kGluon * G.cells + cell] = (2.0 * G.g2 / 8.0) * (16.0 * 3.0 * I[kGluon] + q);
-    for (int i = 0; i < 3; ++i) {
-      const double mq = 2.0 * CF * G.g2 * (2.0 * I[kGluon] + I[i] + I[i + 3]);
-      mass2[i * G.cells + cell] = mq;
-      mass2[(i + 3) * G.cells + cell] = mq;
-    }
+}
+
+__global__ __launch_bounds__(kBlock) void mass_final(Grid G, const double* __restrict__ part, int chunks,
+                                                     double* mass2) {
+  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= G.cells) return;
+  const double meas = G.dp[0] * G.dp[1] * G.dp[2] / (8.0 * kPi * kPi * kPi);
+  double I[kSpecies];
+  for (int sp = 0; sp < kSpecies; ++sp) {
+    double t = 0.0;
+    for (int c = 0; c < chunks; ++c) t += part[((size_t)cell * chunks + c) * kSpecies + sp];
+    I[sp] = t * meas;
+  }
+  // SU(3): dA = 8, CA = 3, CF = 4/3; N_g = 16, N_q = 6
+  const double CF = 4.0 / 3.0;
+  double q = 0.0;
+  for (int i = 0; i < 3; ++i) q += 6.0 * CF * (I[i] + I[i + 3]);
+  mass2[kGluon * G.cells + cell] = (2.0 * G.g2 / 8.0) * (16.0 * 3.0 * I[kGluon] + q);
+  for (int i = 0; i < 3; ++i) {
+    const double mq = 2.0 * CF * G.g2 * (2.0 * I[kGluon] + I[i] + I[i + 3]);
+    mass2[i * G.cells + cell] = mq;
+    mass2[(i + 3) * G.cells + cell] = mq;
   }
 }
 
@@ -208,36 +225,25 @@ __global__ __launch_bounds__(kBlock) void observables_partial(Grid G, const doub
   }
 }
 
-__global__ __launch_bounds__(kBlock) void observables_final(Grid G, const double* partial, int nblocks,
-                                                            double* out) {
-  __shared__ double sh[kBlock / 64];
+// Stage 2: one wave per value (min, max or sum over the block partials).
+constexpr int kFinalThreads = 1024;
+
+__global__ __launch_bounds__(kFinalThreads) void observables_final(Grid G, const double* partial, int nblocks,
+                                                                   double* out) {
   const double meas = G.dx[0] * G.dx[1] * G.dx[2] * G.dp[0] * G.dp[1] * G.dp[2] / (8.0 * kPi * kPi * kPi);
-  for (int k = 0; k < kObs + 3; ++k) {
-    double v = (k == kObs) ? 1e300 : (k == kObs + 1 ? -1e300 : 0.0);
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+  const int lane = threadIdx.x & 63, nw = blockDim.x / 64;
+  for (int k = threadIdx.x / 64; k < kObs + 3; k += nw) {
+    const bool is_min = k == kObs, is_max = k == kObs + 1;
+    double v = is_min ? 1e300 : (is_max ? -1e300 : 0.0);
+    for (int b = lane; b < nblocks; b += 64) {
       const double x = partial[(size_t)b * (kObs + 3) + k];
-      if (k == kObs) v = fmin(v, x);
-      else if (k == kObs + 1) v = fmax(v, x);
-      else v += x;
+      v = is_min ? fmin(v, x) : (is_max ? fmax(v, x) : v + x);
     }
-    if (k == kObs || k == kObs + 1) {
-      for (int off = 32; off > 0; off >>= 1) {
-        const double o = __shfl_xor(v, off, 64);
-        v = (k == kObs) ? fmin(v, o) : fmax(v, o);
-      }
-      __shared__ double shm[kBlock / 64];
-      const int w = threadIdx.x / 64, lane = threadIdx.x & 63;
-      __syncthreads();
-      if (lane == 0) shm[w] = v;
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        for (int i = 1; i < (int)(blockDim.x / 64); ++i) v = (k == kObs) ? fmin(v, shm[i]) : fmax(v, shm[i]);
-        out[k] = v;
-      }
-    } else {
-      const double t = block_sum(v, sh);
-      if (threadIdx.x == 0) out[k] = (k < kObs) ? t * degeneracy(k / kObsPer) * meas : t;
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_xor(v, off, 64);
+      v = is_min ? fmin(v, o) : (is_max ? fmax(v, o) : v + o);
     }
+    if (lane == 0) out[k] = (k < kObs) ? v * degeneracy(k / kObsPer) * meas : v;
   }
 }
 
@@ -321,8 +327,14 @@ unsigned grid_for(size_t n) {
 
 }  // namespace
 
-hipError_t launch_masses(const Grid& G, const double* f, const double* lag, double* mass2, hipStream_t st) {
-  hipLaunchKernelGGL(mass_kernel, dim3(G.cells), dim3(kBlock), 0, st, G, f, lag, mass2);
+size_t mass_scratch(const Grid& G) { return (size_t)G.cells * mass_chunks(G) * kSpecies; }
+
+hipError_t launch_masses(const Grid& G, const double* f, const double* lag, double* scratch, double* mass2,
+                         hipStream_t st) {
+  const int chunks = mass_chunks(G);
+  hipLaunchKernelGGL(mass_partial, dim3(chunks, G.cells), dim3(kBlock), 0, st, G, f, lag, scratch);
+  hipLaunchKernelGGL(mass_final, dim3((G.cells + kBlock - 1) / kBlock), dim3(kBlock), 0, st, G, scratch, chunks,
+                     mass2);
   return hipGetLastError();
 }
 
@@ -351,7 +363,7 @@ hipError_t launch_observables(const Grid& G, const double* f, const double* mass
                               double* out, hipStream_t st) {
   const int nb = observables_blocks(G);
   hipLaunchKernelGGL(observables_partial, dim3(nb), dim3(kBlock), 0, st, G, f, mass2, scratch);
-  hipLaunchKernelGGL(observables_final, dim3(1), dim3(kBlock), 0, st, G, scratch, nb, out);
+  hipLaunchKernelGGL(observables_final, dim3(1), dim3(kFinalThreads), 0, st, G, scratch, nb, out);
   return hipGetLastError();
 }
 

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(PKG, "libqgbe.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ESTATE, ENUMERIC, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 FP64, FP32 = 0, 1
-SAMPLER_UNIFORM, SAMPLER_LEARNED = 0, 1
+SAMPLER_UNIFORM, SAMPLER_LEARNED, SAMPLER_ROOTS, SAMPLER_ROOTS_ALT = 0, 1, 2, 3
 DRIFT_UPWIND, DRIFT_CENTRAL = 0, 1
 MASS_DYNAMIC, MASS_CONSTANT = 0, 1
 FLAG_NEGATIVE_F, FLAG_PAULI, FLAG_NONFINITE = 1, 2, 4

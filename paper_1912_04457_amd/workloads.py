@@ -42,6 +42,7 @@ class Workload:
     alpha_s: float = 0.3
     row_mask: int = ALL_ROWS
     init: dict = field(default_factory=dict)
+    symmetric: bool = True
 
     @property
     def cells(self) -> int:
@@ -68,7 +69,14 @@ C4 = replace(C3, name="qg7_1cell_20cube_learned", sampler="learned")
 C5 = Workload("qg7_12cube_16cube_learned", (12, 12, 12), (16, 16, 16), (6.0, 6.0, 6.0),
               (3.0, 3.0, 3.0), ALL_SPECIES, 256, "f32", 50, 0.01, sampler="learned",
               init=dict(kind="blobs_fd", Qs=1.0, T=0.3, n_blobs=3, seed=BLOB_SEED))
-WORKLOADS = {w.name: w for w in (C1, C2, C3, C4, C5)}
+# The stability test of Sec. IV A: f uniform in [0, 1] on 40^3 nodes, 100
+# samples per node, one step of the direct estimator, with the paper's root
+# parameterisation (and its alternative elimination).
+ROOTS = Workload("g_1cell_40cube_roots", (1, 1, 1), (40, 40, 40), (3.0, 3.0, 3.0), (2.0, 2.0, 2.0),
+                 1 << GLUON, 100, "f64", 1, 0.01, sampler="roots", symmetric=False,
+                 init=dict(kind="uniform", seed=7))
+ROOTS_ALT = replace(ROOTS, name="g_1cell_40cube_roots_alt", sampler="roots_alt")
+WORKLOADS = {w.name: w for w in (C1, C2, C3, C4, C5, ROOTS, ROOTS_ALT)}
 
 
 def node_momenta(n_p, p_half) -> np.ndarray:
@@ -114,6 +122,9 @@ def initial_f(wl: Workload) -> np.ndarray:
         else:
             f0 = blob_profile(wl, X, ini)
             f[GLUON] = f0[:, None] * step[None, :]
+    elif kind == "uniform":
+        rng = np.random.Generator(np.random.PCG64(ini.get("seed", 7)))
+        f[GLUON] = rng.uniform(0.0, 1.0, size=(wl.cells, wl.nodes))
     else:
         raise ValueError(f"unknown initial condition {kind}")
     for sp in range(7):

@@ -390,6 +390,33 @@ def modified_energy(grid: Grid, f, mass2) -> float:
     return float(T - 0.25 * (DEGENERACY[:, None, None] * term).sum() * meas)
 
 
+def thermo(grid: Grid, f, mass2) -> dict:
+    """Entropy and the diagonal of Eq. energy momentum tensor.
+
+    entropy = sum N dV [(1 + s f) ln(1 + s f)/s - f ln f], s = +1 for gluons
+    and -1 for quarks, over the nodes with f > 0 and 1 + s f > 0 (the others
+    add nothing); T_ii = sum N dV p_i^2 f / E over nodes with E > 0.
+    """
+    f = _field(grid, f)
+    meas = _cell_measure(grid)
+    E = _energies(grid, mass2)
+    S = 0.0
+    for sp in range(7):
+        s = 1.0 if sp == GLUON else -1.0
+        fv = f[sp]
+        one = 1.0 + s * fv
+        ok = (fv > 0.0) & (one > 0.0)
+        term = one[ok] * np.log(one[ok]) / s - fv[ok] * np.log(fv[ok])
+        S += DEGENERACY[sp] * term.sum()
+    P = grid.momenta()
+    T = np.zeros(3)
+    for a in range(3):
+        with np.errstate(divide="ignore", invalid="ignore"):
+            w = np.where(E > 0.0, f / np.where(E > 0.0, E, 1.0), 0.0)
+        T[a] = (DEGENERACY[:, None, None] * w * (P[:, a] ** 2)[None, None, :]).sum()
+    return dict(entropy=float(S * meas), T_ii=T * meas)
+
+
 @dataclass
 class State:
     """Evolving state of the oracle's time stepper."""
@@ -421,5 +448,6 @@ def step(grid: Grid, state: State, dt_fm: float, n_samples: int, seed: int, *,
     obs["mass2"] = m2
     obs.update(budget)
     obs["E_total_mod"] = modified_energy(grid, state.f, m2)
+    obs.update(thermo(grid, state.f, m2))
     state.history.append(obs)
     return obs

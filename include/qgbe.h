@@ -132,6 +132,14 @@ typedef struct {
   double E_source;
   double E_collide;
   double E_total_mod;
+  /* Thermalisation diagnostics (Sec. IV C, D): the Boltzmann entropy
+   * sum N dV [(1 + s f) ln(1 + s f)/s - f ln f] (s = +1 gluons, -1 quarks;
+   * nodes with f <= 0 or 1 + s f <= 0 add nothing), which the collision term
+   * does not decrease, and the diagonal of Eq. energy momentum tensor,
+   * T_ii = sum N dV p_i^2 f / E (GeV), whose ratio T_zz / T_xx measures the
+   * isotropisation.                                                          */
+  double entropy;
+  double T_ii[3];
 } qgbe_stats;
 
 /* Optional outputs of the collision term (all may be NULL). */

@@ -58,6 +58,8 @@ CollideArgs base_args(qgbe_ctx* c, int n_samples, double* A, double* scale, doub
   a.f64 = c->d_f;
   a.f32 = c->d_f32;
   a.mass2 = c->d_mass2;
+  a.win_lo = 0;
+  a.win_n = c->G.nodes;
   a.A = A;
   a.scale = scale;
   a.items = items;
@@ -134,9 +136,19 @@ void plan_groups(qgbe_ctx* c) {
   c->group_index.clear();
   c->groups.clear();
   for (int nslot = 1; nslot <= 3; ++nslot) {
-    Group g{(int)c->group_index.size(), 0, nslot, {0, 0}, {0, 0}, false};
+    Group g{(int)c->group_index.size(), 0, nslot, {0, 0}, {0, 0}, {c->G.nodes, c->G.nodes}, false};
     for (int l = 0; l < 2; ++l) {
       const size_t budget = c->lds_budget[l];
+      if (c->d.symmetric && budget < acc_b) {
+        // one slot's FP64 accumulators exceed LDS: node windows, one launch
+        // per window and slot, the same samples in each; f from the quads
+        const int fit = (int)(budget / sizeof(double));
+        const int n_win = (c->G.nodes + fit - 1) / fit;
+        g.win[l] = (c->G.nodes + n_win - 1) / n_win;
+        g.lds_acc[l] = 1;
+        g.lds_tiles[l] = 0;
+        continue;
+      }
       g.lds_acc[l] = c->d.symmetric ? (int)std::min<size_t>(nslot, budget / acc_b) : 0;
       g.lds_tiles[l] = (int)std::min<size_t>(nslot, (budget - g.lds_acc[l] * acc_b) / tile_b);
     }
@@ -202,18 +214,23 @@ qgbe_status run_collide(qgbe_ctx* c, int n_samples, int sampler, double* A, doub
     const int per = g.lds_acc[l];
     const int n_pass = (c->d.symmetric && per >= 1 && per < g.nslot) ? (g.nslot + per - 1) / per : 1;
     const size_t acc_b = (size_t)c->G.nodes * sizeof(double), tile_b = (size_t)c->G.nodes * sizeof(float);
+    const int win = g.win[l], n_win = (c->G.nodes + win - 1) / win;
     for (int pass = 0; pass < n_pass; ++pass) {
-      a.slot_lo = n_pass > 1 ? pass * per : 0;
-      a.slot_hi = n_pass > 1 ? std::min(g.nslot, a.slot_lo + per) : g.nslot;
-      a.direct = pass == 0 ? 1 : 0;
-      a.lds_acc = g.lds_acc[l];
-      a.lds_tiles = g.lds_tiles[l];
-      if (n_pass > 1) {
-        const size_t used = (size_t)(a.slot_hi - a.slot_lo) * acc_b;
-        a.lds_tiles = (int)std::min<size_t>(g.nslot, (c->lds_budget[l] - used) / tile_b);
+      for (int w = 0; w < n_win; ++w) {
+        a.slot_lo = n_pass > 1 ? pass * per : 0;
+        a.slot_hi = n_pass > 1 ? std::min(g.nslot, a.slot_lo + per) : g.nslot;
+        a.win_lo = w * win;
+        a.win_n = std::min(win, c->G.nodes - a.win_lo);
+        a.direct = pass == 0 && w == 0 ? 1 : 0;
+        a.lds_acc = g.lds_acc[l];
+        a.lds_tiles = g.lds_tiles[l];
+        if (n_pass > 1 && n_win == 1) {
+          const size_t used = (size_t)(a.slot_hi - a.slot_lo) * acc_b;
+          a.lds_tiles = (int)std::min<size_t>(g.nslot, (c->lds_budget[l] - used) / tile_b);
+        }
+        if (queue) a.lds_tiles = 0;  // the compacting variant reads f from the node quads
+        HIP_TRY(launch_collide_f32(a, g.nslot, queue && n_pass == 1 && n_win == 1, c->stream), "collide (fp32)");
       }
-      if (queue) a.lds_tiles = 0;  // the compacting variant reads f from the node quads
-      HIP_TRY(launch_collide_f32(a, g.nslot, queue && n_pass == 1, c->stream), "collide (fp32)");
     }
   }
   return QGBE_OK;
@@ -229,6 +246,8 @@ void fill_stats(qgbe_ctx* c, const double* obs, const double* mass2_host, qgbe_s
     st->E_total += st->E[s];
     for (int k = 0; k < 3; ++k) st->P[k] += obs[s * kObsPer + 2 + k];
     mass_term += obs[s * kObsPer + 5];
+    st->entropy += obs[s * kObsPer + 6];
+    for (int k = 0; k < 3; ++k) st->T_ii[k] += obs[s * kObsPer + 7 + k];
     double m = 0.0;
     for (int x = 0; x < c->G.cells; ++x) m += mass2_host[s * c->G.cells + x];
     st->mass2_avg[s] = m / c->G.cells;

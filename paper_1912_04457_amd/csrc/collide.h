@@ -17,6 +17,8 @@ struct CollideArgs {
   int lds_acc;            // FP64 deposit accumulators in LDS (FP32 kernel)
   int slot_lo, slot_hi;   // deposit slots [lo, hi) written by this launch (FP32 kernel); the
                           // first lds_acc of them accumulate in LDS, the rest in global memory
+  int win_lo, win_n;      // LDS accumulators cover nodes [win_lo, win_lo + win_n) (FP32 kernel);
+                          // deposit corners outside belong to another launch
   int direct;             // this launch also writes the direct sums, items, scale and counts
   int n_samples;
   int symmetric;

@@ -230,6 +230,24 @@ __device__ __forceinline__ void deposit(T* acc, const Stencil<R>& st, R v, int o
   __hip_atomic_fetch_add(q + ox + oy + 1, (T)(v11 * st.wz), __ATOMIC_RELAXED, kScope);
 }
 
+// The same deposit into accumulators that cover only the nodes [lo, lo + n)
+// (acc[0] is node lo): the same corner values; a corner outside the window
+// is left to the launch whose window holds it.
+__device__ __forceinline__ void deposit_window(double* acc, const Stencil<double>& st, double v, int ox, int oy,
+                                               int lo, int n) {
+  const int b = st.base - lo;
+  const double vx1 = v * st.wx, vx0 = v - vx1;
+  const double v01 = vx0 * st.wy, v00 = vx0 - v01;
+  const double v11 = vx1 * st.wy, v10 = vx1 - v11;
+  const int off[8] = {0, 1, oy, oy + 1, ox, ox + 1, ox + oy, ox + oy + 1};
+  const double val[8] = {v00 - v00 * st.wz, v00 * st.wz, v01 - v01 * st.wz, v01 * st.wz,
+                         v10 - v10 * st.wz, v10 * st.wz, v11 - v11 * st.wz, v11 * st.wz};
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+    if ((unsigned)(b + off[c]) < (unsigned)n)
+      __hip_atomic_fetch_add(acc + b + off[c], val[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // 1 / ((2 pi)^3 * 2 * 2 * 16 pi^2): two-body phase space |p*|/(16 pi^2 sqrt s),
 // k2 measure d^3k2/((2 pi)^3 2 E2) and 1/(2 E1) of Eq. C_a_b
 constexpr double kNorm = 1.0 / (8.0 * kPi * kPi * kPi * 4.0 * 16.0 * kPi * kPi);
@@ -900,13 +918,17 @@ __device__ __forceinline__ Stencil<double> widen(const Stencil<float>& st) {
 template <bool kAllLds>
 __device__ __forceinline__ void deposit_slot(int k, int slot_lo, int slot_hi, int n_acc, double* acc,
                                              double* __restrict__ out, size_t off, const Stencil<float>& st,
-                                             float v, int nodes, int ox, int oy) {
+                                             float v, int nodes, int ox, int oy, int win_lo, int win_n) {
   if (k < slot_lo || k >= slot_hi) return;  // deposited by another launch
   const int j = k - slot_lo;
-  if (kAllLds || j < n_acc)
-    deposit<double, double, __HIP_MEMORY_SCOPE_WORKGROUP>(acc + j * nodes, widen(st), (double)v, ox, oy);
-  else
+  if (kAllLds || j < n_acc) {
+    if (win_n == nodes)  // (wave-uniform) the whole grid in LDS
+      deposit<double, double, __HIP_MEMORY_SCOPE_WORKGROUP>(acc + j * win_n, widen(st), (double)v, ox, oy);
+    else
+      deposit_window(acc + j * win_n, widen(st), (double)v, ox, oy, win_lo, win_n);
+  } else {
     deposit<double, double>(out + off, widen(st), (double)v, ox, oy);
+  }
 }
 
 // Workgroups are dispatched to the 8 XCDs in turn (workgroup b to XCD b mod
@@ -966,14 +988,15 @@ __global__ __launch_bounds__(f32_block(kLearned, kQueue)) void collide_f32_kerne
   const int nodes = G.nodes;
   const int n_acc = kSym ? min(A.slot_hi - A.slot_lo, A.lds_acc) : 0;
   const int n_tiles = min(nslot, A.lds_tiles);
-  double* acc = lds;                                          // [n_acc][nodes], slots slot_lo..
-  float* tiles = reinterpret_cast<float*>(lds + (size_t)n_acc * nodes);  // [n_tiles][nodes]
+  const int win_lo = A.win_lo, win_n = A.win_n;
+  double* acc = lds;                                          // [n_acc][win_n], slots slot_lo..
+  float* tiles = reinterpret_cast<float*>(lds + (size_t)n_acc * win_n);  // [n_tiles][nodes]
   size_t goff[3];  // offsets of the slots' (species, cell) rows in f32 and A
   for (int k = 0; k < 3; ++k) {
     const int sp = k < nslot ? ch.slot_sp[k] : ch.slot_sp[0];
     goff[k] = ((size_t)sp * G.cells + cell) * nodes;
   }
-  for (int i = threadIdx.x; i < n_acc * nodes; i += blockDim.x) acc[i] = 0.0;
+  for (int i = threadIdx.x; i < n_acc * win_n; i += blockDim.x) acc[i] = 0.0;
   if (threadIdx.x < 2) mc_wg[threadIdx.x] = 0.0;
   if (threadIdx.x == 0) ok_wg = 0ull;
   for (int k = 0; k < n_tiles; ++k)
@@ -1034,9 +1057,12 @@ __global__ __launch_bounds__(f32_block(kLearned, kQueue)) void collide_f32_kerne
         if (kQueue) {
           pd2 = s2; pd3 = s3; pd4 = s4; pdv = v;
         } else {
-          deposit_slot<kAccLds>(k2, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off2, s2, v, nodes, G.ox, G.oy);
-          deposit_slot<kAccLds>(k3, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off3, s3, -v, nodes, G.ox, G.oy);
-          deposit_slot<kAccLds>(k4, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off4, s4, -v, nodes, G.ox, G.oy);
+          deposit_slot<kAccLds>(k2, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off2, s2, v,
+                                nodes, G.ox, G.oy, win_lo, win_n);
+          deposit_slot<kAccLds>(k3, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off3, s3, -v,
+                                nodes, G.ox, G.oy, win_lo, win_n);
+          deposit_slot<kAccLds>(k4, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off4, s4, -v,
+                                nodes, G.ox, G.oy, win_lo, win_n);
         }
         if (kScale && A.direct) {
           const float vs = fabsf(wnb) * (gain + loss);
@@ -1071,12 +1097,14 @@ __global__ __launch_bounds__(f32_block(kLearned, kQueue)) void collide_f32_kerne
         const int s = base + lane;
         uint32_t x0 = (uint32_t)s, x1 = (uint32_t)p1_lin, x2 = (uint32_t)cell, x3 = ((uint32_t)ch.code << 8);
         philox4x32_10(x0, x1, x2, x3, A.key0, A.key1);
-        if (pending) deposit_slot<true>(k2, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off2, pd2, pdv, nodes, G.ox, G.oy);
+        if (pending) deposit_slot<true>(k2, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off2, pd2, pdv,
+                                        nodes, G.ox, G.oy, win_lo, win_n);
         double u[5];
         five_uniforms(x0, x1, x2, x3, u);
         Geo g;
         const bool ok = s < A.n_samples && geometry(it, G, u, g);
-        if (pending) deposit_slot<true>(k3, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off3, pd3, -pdv, nodes, G.ox, G.oy);
+        if (pending) deposit_slot<true>(k3, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off3, pd3, -pdv,
+                                        nodes, G.ox, G.oy, win_lo, win_n);
         const unsigned long long mask = __ballot(ok);
         if (ok) {
           const unsigned slot = (tail + (unsigned)__popcll(mask & ((1ull << lane) - 1ull))) & (kQueueLen - 1);
@@ -1089,7 +1117,8 @@ __global__ __launch_bounds__(f32_block(kLearned, kQueue)) void collide_f32_kerne
           q_f[wid][2][slot] = (float)g.u;
           q_f[wid][3][slot] = prefactor<float>(it, g);
         }
-        if (pending) deposit_slot<true>(k4, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off4, pd4, -pdv, nodes, G.ox, G.oy);
+        if (pending) deposit_slot<true>(k4, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off4, pd4, -pdv,
+                                        nodes, G.ox, G.oy, win_lo, win_n);
         pending = false;
         tail += (unsigned)__popcll(mask);
         if (tail - head >= (unsigned)kWave) {
@@ -1102,9 +1131,12 @@ __global__ __launch_bounds__(f32_block(kLearned, kQueue)) void collide_f32_kerne
         }
       }
       auto flush = [&]() {
-        deposit_slot<true>(k2, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off2, pd2, pdv, nodes, G.ox, G.oy);
-        deposit_slot<true>(k3, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off3, pd3, -pdv, nodes, G.ox, G.oy);
-        deposit_slot<true>(k4, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off4, pd4, -pdv, nodes, G.ox, G.oy);
+        deposit_slot<true>(k2, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off2, pd2, pdv,
+                           nodes, G.ox, G.oy, win_lo, win_n);
+        deposit_slot<true>(k3, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off3, pd3, -pdv,
+                           nodes, G.ox, G.oy, win_lo, win_n);
+        deposit_slot<true>(k4, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off4, pd4, -pdv,
+                           nodes, G.ox, G.oy, win_lo, win_n);
       };
       if (pending) flush();  // the last full batch
       if (tail != head) {    // the last, partial batch
@@ -1153,11 +1185,11 @@ __global__ __launch_bounds__(f32_block(kLearned, kQueue)) void collide_f32_kerne
   if (threadIdx.x == 0 && A.n_accepted && A.direct) atomicAdd(A.n_accepted, ok_wg);
   if (threadIdx.x == 0 && A.chan_var && A.direct) atomicAdd(&A.chan_var[ci], mc_wg[0]);  // one channel per workgroup
   if (n_acc > 0) {
-    for (int i = threadIdx.x; i < n_acc * nodes; i += blockDim.x) {
+    for (int i = threadIdx.x; i < n_acc * win_n; i += blockDim.x) {
       const double v = acc[i];
       if (v != 0.0) {
-        const int j = i / nodes;
-        atomicAdd(A.A + goff[A.slot_lo + j] + (i - j * nodes), v);
+        const int j = i / win_n;
+        atomicAdd(A.A + goff[A.slot_lo + j] + win_lo + (i - j * win_n), v);
       }
     }
   }
@@ -1292,9 +1324,9 @@ hipError_t launch_collide_f32(const CollideArgs& a, int nslot, bool queue, hipSt
   // variant without global-memory paths
   const bool all_acc = !a.symmetric || n_acc == a.slot_hi - a.slot_lo;
   const bool all_lds = n_tiles == nslot && all_acc;
-  queue = queue && all_acc && a.symmetric && !a.learned;
+  queue = queue && all_acc && a.symmetric && !a.learned && a.win_n == a.G.nodes;
   const int threads = f32_block(a.learned != 0, queue);
-  const size_t lds = (size_t)n_acc * a.G.nodes * sizeof(double) + (size_t)n_tiles * a.G.nodes * sizeof(float);
+  const size_t lds = (size_t)n_acc * a.win_n * sizeof(double) + (size_t)n_tiles * a.G.nodes * sizeof(float);
   const long long blocks = (long long)a.G.cells * a.n_group * a.n_chunks;
   if (blocks <= 0) return hipSuccess;
   const dim3 grid((unsigned)blocks), block(threads);

@@ -29,6 +29,8 @@ struct Group {
   int nslot;          // distinct species at positions 2..4
   int lds_acc[2];     // FP64 accumulators staged in LDS  [uniform, learned sampler]
   int lds_tiles[2];   // FP32 f tiles staged in LDS       [uniform, learned sampler]
+  int win[2];         // nodes per accumulator window (= nodes unless one slot's FP64
+                      // accumulators exceed LDS; then one launch per window and slot)
   bool queue;         // the uniform sampler's compacting variant fits
 };
 

@@ -10,9 +10,10 @@ struct Mass7 {
 };
 
 // Observables layout in `out` (length observables_len): per species
-// [N, E, Px, Py, Pz, M] (7 x 6) with M = sum N dV m^2 f / E, then min f,
-// max fermion f, non-finite count.
-constexpr int kObsPer = 6;
+// [N, E, Px, Py, Pz, M, S, Txx, Tyy, Tzz] (7 x 10) with M = sum N dV m^2 f / E,
+// S the entropy and Tii = sum N dV p_i^2 f / E, then min f, max fermion f,
+// non-finite count.
+constexpr int kObsPer = 10;
 constexpr int observables_len = kSpecies * kObsPer + 3;
 
 // Thermal masses (Eq. mg, Eq. mq); scratch holds mass_scratch(G) doubles.

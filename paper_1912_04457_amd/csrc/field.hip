@@ -167,9 +167,12 @@ __global__ __launch_bounds__(kBlock) void update_kernel(Grid G, const double* __
   }
 }
 
-// Observables: per species N, E, P (3) and M = sum m^2 f / E (the mass term
-// of the modified tensor), then min f and max fermion f, and a non-finite
-// counter.  Stage 1: per-block partials; stage 2: one block.
+// Observables: per species N, E, P (3), M = sum m^2 f / E (the mass term of
+// the modified tensor), the entropy S = sum [(1 + s f) ln(1 + s f)/s - f ln f]
+// (s = +1 for gluons, -1 for quarks; a node adds only while 0 < f and
+// 1 + s f > 0) and the diagonal T^ii = sum p_i^2 f / E of Eq. energy momentum
+// tensor, then min f and max fermion f, and a non-finite counter.  Stage 1:
+// per-block partials; stage 2: one block.
 constexpr int kObs = kSpecies * kObsPer;
 
 __global__ __launch_bounds__(kBlock) void observables_partial(Grid G, const double* __restrict__ f,
@@ -179,8 +182,9 @@ __global__ __launch_bounds__(kBlock) void observables_partial(Grid G, const doub
   const size_t per = (size_t)G.cells * G.nodes;
   double minf = 1e300, maxq = -1e300, bad = 0.0;
   for (int sp = 0; sp < kSpecies; ++sp) {
-    double N = 0.0, E = 0.0, P0 = 0.0, P1 = 0.0, P2 = 0.0, M = 0.0;
+    double N = 0.0, E = 0.0, P0 = 0.0, P1 = 0.0, P2 = 0.0, M = 0.0, S = 0.0, T0 = 0.0, T1 = 0.0, T2 = 0.0;
     const bool evolve = (G.species_mask >> sp) & 1u;
+    const double sgn = sp == kGluon ? 1.0 : -1.0;
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < per; i += (size_t)gridDim.x * blockDim.x) {
       const int cell = (int)(i / G.nodes), node = (int)(i % G.nodes);
       const double fv = f[(size_t)sp * per + i];
@@ -190,7 +194,15 @@ __global__ __launch_bounds__(kBlock) void observables_partial(Grid G, const doub
       const double En = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2] + m2);
       N += fv;
       E += En * fv;
-      if (En > 0.0) M += m2 * fv / En;
+      if (En > 0.0) {
+        const double w = fv / En;
+        M += m2 * w;
+        T0 += p[0] * p[0] * w;
+        T1 += p[1] * p[1] * w;
+        T2 += p[2] * p[2] * w;
+      }
+      const double one = 1.0 + sgn * fv;
+      if (fv > 0.0 && one > 0.0) S += one * log(one) * sgn - fv * log(fv);
       P0 += p[0] * fv;
       P1 += p[1] * fv;
       P2 += p[2] * fv;
@@ -200,7 +212,7 @@ __global__ __launch_bounds__(kBlock) void observables_partial(Grid G, const doub
         if (sp != kGluon) maxq = fmax(maxq, fv);
       }
     }
-    const double vals[kObsPer] = {N, E, P0, P1, P2, M};
+    const double vals[kObsPer] = {N, E, P0, P1, P2, M, S, T0, T1, T2};
     for (int k = 0; k < kObsPer; ++k) {
       const double t = block_sum(vals[k], sh);
       if (threadIdx.x == 0) partial[(size_t)blockIdx.x * (kObs + 3) + sp * kObsPer + k] = t;

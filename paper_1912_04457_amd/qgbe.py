@@ -60,7 +60,8 @@ class Stats(C.Structure):
                 ("min_f", C.c_double), ("max_fermion_f", C.c_double), ("n_evals", C.c_double),
                 ("t_collide_ms", C.c_double), ("t_step_ms", C.c_double), ("flags", C.c_uint32),
                 ("step", C.c_uint32), ("n_accepted", C.c_double), ("mc_err_est", C.c_double),
-                ("E_source", C.c_double), ("E_collide", C.c_double), ("E_total_mod", C.c_double)]
+                ("E_source", C.c_double), ("E_collide", C.c_double), ("E_total_mod", C.c_double),
+                ("entropy", C.c_double), ("T_ii", C.c_double * 3)]
 
     def as_dict(self) -> dict:
         out = {}

@@ -106,12 +106,14 @@ def test_config3_lds_layout_fp32(O):
     assert abs(r["A"].sum()) <= 1e-13 * r["S_ref"].sum()
 
 
-@pytest.mark.parametrize("n_p,mask,N", [((32, 32, 32), 1 << 6, 4), ((24, 24, 24), 0x7F, 2)],
-                         ids=["g_32cube", "qg7_24cube"])
+@pytest.mark.parametrize("n_p,mask,N", [((32, 32, 32), 1 << 6, 4), ((24, 24, 24), 0x7F, 2),
+                                         ((28, 28, 28), 0x7F, 1)],
+                         ids=["g_32cube", "qg7_24cube", "qg7_28cube"])
 def test_large_grid_lds_plans_fp32(O, n_p, mask, N):
-    """Grids whose FP64 accumulators do not fit in LDS (32^3: none, global
-    atomics; 24^3: one per launch) next to FP32 tiles in LDS or in the
-    global node quads."""
+    """Grids whose FP64 accumulators do not fit in LDS: 24^3 holds one slot
+    per launch; at 32^3 and 28^3 not even one slot fits, and each slot runs
+    as two node windows (launches whose accumulators cover half the nodes,
+    corners outside left to the other), f from the global node quads."""
     _case(f"large grid {n_p} mask={mask:#x} N={N}")
     wl = W.C3.scaled(n_p=n_p, species_mask=mask)
     f = W.initial_f(wl)
@@ -167,6 +169,8 @@ def test_step_parity_fp64(O):
         assert abs(a["E_source"] - b["E_source"]) <= 1e-12 * b["E_total"]
         assert abs(a["E_collide"] - b["E_collide"]) <= 1e-12 * b["E_total"]
         assert a["E_total_mod"] == pytest.approx(b["E_total_mod"], rel=1e-12)
+        assert a["entropy"] == pytest.approx(b["entropy"], rel=1e-12)
+        assert np.allclose(a["T_ii"], b["T_ii"], rtol=1e-12)
     assert stats[0]["E_source"] == 0.0 and stats[1]["E_source"] != 0.0
     N0 = O.observables(g, f0, O.masses(g, f0))["N_total"]
     assert abs(stats[-1]["N_total"] - N0) <= 1e-13 * N0

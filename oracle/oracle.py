@@ -95,6 +95,8 @@ def lib():
                                                p, p, p, i32]
         _lib.ref_item_sums.restype = i32
         _lib.ref_item_sums.argtypes = [p, p, p, u64, u32, i32, i32, C.c_int64, p, p, p, i32]
+        _lib.ref_set_matrix_element.restype = i32
+        _lib.ref_set_matrix_element.argtypes = [i32, i32, p, p]
         _lib.ref_item_sums_est.restype = i32
         _lib.ref_item_sums_est.argtypes = [p, p, p, u64, u32, i32, i32, i32, C.c_int64, p, p, p, i32]
         _lib.ref_collision_points.restype = i32
@@ -157,6 +159,17 @@ def philox4x32_10(ctr, key) -> np.ndarray:
 
 def msq(row: int, s: float, t: float, u: float, mg2: float, alpha_s: float) -> float:
     return lib().ref_msq(row, s, t, u, mg2, alpha_s)
+
+
+def set_matrix_element(row: int, terms) -> None:
+    """Replace Table I row `row` by g^4 sum_k c_k s^a t^b u^c / ((t - m_g^2)^d
+    (u - m_g^2)^e s^f); terms = [(c, (a, b, c, d, e, f)), ...]; [] restores it.
+    Process-wide (call with [] when done)."""
+    coef = np.ascontiguousarray([t[0] for t in terms], dtype=np.float64)
+    powers = np.ascontiguousarray([t[1] for t in terms], dtype=np.int32).reshape(-1, 6)
+    if lib().ref_set_matrix_element(row, len(terms), _ptr(coef) if len(terms) else None,
+                                    powers.ctypes.data_as(C.c_void_p) if len(terms) else None) < 0:
+        raise ValueError("bad matrix element terms")
 
 
 def channels(grid: Grid) -> list[dict]:

@@ -71,10 +71,45 @@ static double unif23(uint32_t v) { return ((double)v + 0.5) / 8388608.0; }
 /* Table I: |M|^2 summed over colours and helicities, every t and u   */
 /* pole regulated by the gluon thermal mass m_g^2.                     */
 /* ------------------------------------------------------------------ */
+/* User matrix elements (Sec. II: an interface for matrix elements of the
+   user's own).  A row set here replaces Table I for every channel of that
+   row: |M|^2 = g^4 sum_k c_k s^a t^b u^c / ((t - mg2)^d (u - mg2)^e s^f).
+   Process-wide state of the test oracle; n = 0 restores Table I. */
+static struct {
+  int n;
+  double c[REF_MSQ_MAX_TERMS];
+  int p[REF_MSQ_MAX_TERMS][6];
+} g_user_msq[8];
+
+int32_t ref_set_matrix_element(int32_t row, int32_t n, const double* coef, const int32_t* powers) {
+  if (row < 1 || row > 7 || n < 0 || n > REF_MSQ_MAX_TERMS) return -1;
+  for (int k = 0; k < n; ++k)
+    for (int i = 0; i < 6; ++i)
+      if (powers[6 * k + i] < 0 || powers[6 * k + i] > REF_MSQ_MAX_POWER) return -1;
+  g_user_msq[row].n = n;
+  for (int k = 0; k < n; ++k) {
+    g_user_msq[row].c[k] = coef[k];
+    for (int i = 0; i < 6; ++i) g_user_msq[row].p[k][i] = powers[6 * k + i];
+  }
+  return 0;
+}
+
+static double user_msq(int row, double s, double t, double u, double mg2) {
+  double sum = 0.0;
+  for (int k = 0; k < g_user_msq[row].n; ++k) {
+    const int* e = g_user_msq[row].p[k];
+    const double num = pow(s, e[0]) * pow(t, e[1]) * pow(u, e[2]);
+    const double den = pow(t - mg2, e[3]) * pow(u - mg2, e[4]) * pow(s, e[5]);
+    sum += g_user_msq[row].c[k] * num / den;
+  }
+  return sum;
+}
+
 double ref_msq(int32_t row, double s, double t, double u, double mg2, double alpha_s) {
   const double g2 = 4.0 * PI * alpha_s;
   const double g4 = g2 * g2;
   const double tm = t - mg2, um = u - mg2;
+  if (row >= 1 && row <= 7 && g_user_msq[row].n > 0) return g4 * user_msq(row, s, t, u, mg2);
   const double c_qq = 8.0 * g4 * D_F * D_F * C_F * C_F / D_A;       /* 8 g^4 dF^2 CF^2 / dA */
   const double c_int = 16.0 * g4 * D_F * C_F * (C_F - C_A / 2.0);    /* interference         */
   switch (row) {

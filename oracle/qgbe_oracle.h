@@ -88,8 +88,16 @@ enum { REF_EST_CM = 0, REF_EST_ROOT = 1, REF_EST_ROOT_K3 = 2 };
 /* Philox4x32-10 block (Salmon et al., SC'11) */
 void ref_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 
-/* |M|^2 of Table I (summed over all colours and helicities) */
+/* |M|^2 of Table I (summed over all colours and helicities), or the user's
+   matrix element of that row (ref_set_matrix_element) */
 double ref_msq(int32_t row, double s, double t, double u, double mg2, double alpha_s);
+
+/* replace Table I row `row` (1..7) by g^4 sum_k c_k s^a t^b u^c /
+   ((t - mg2)^d (u - mg2)^e s^f), powers[k] = {a, b, c, d, e, f} in
+   0..REF_MSQ_MAX_POWER, n <= REF_MSQ_MAX_TERMS terms; n = 0 restores the
+   row.  Returns -1 on bad arguments. */
+enum { REF_MSQ_MAX_TERMS = 8, REF_MSQ_MAX_POWER = 4 };
+int32_t ref_set_matrix_element(int32_t row, int32_t n, const double* coef, const int32_t* powers);
 
 /* channel table for the species/row masks, in ascending order of code;
    returns the count (<= max) */

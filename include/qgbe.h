@@ -231,6 +231,21 @@ qgbe_status qgbe_restore(qgbe_ctx* ctx, const void* buf, size_t bytes);
 qgbe_status qgbe_collision_term(qgbe_ctx* ctx, int32_t n_samples, int32_t sampler,
                                 double* A_out, int32_t on_device, qgbe_stats* st);
 
+/* User matrix elements (Sec. II: the tree-level Table I is the default and
+ * users may supply their own).  Replaces row `row` (1..7) of Table I, for
+ * every channel of that row, by
+ *   |M|^2 = g^4 sum_{k < n_terms} coef[k] s^a t^b u^c / ((t - m_g^2)^d (u - m_g^2)^e s^f)
+ * with g^2 = 4 pi alpha_s, the Mandelstam variables of the row's labelling
+ * (Table I) and powers[6 k .. 6 k + 5] = {a, b, c, d, e, f}, each 0..4;
+ * n_terms <= 8, and n_terms = 0 restores the Table I row.  Table I itself is
+ * of this form (e.g. row 7 = 3456 - 1152 su/(t-m^2)^2 - 1152 st/(u-m^2)^2 -
+ * 1152 tu/s^2).  Takes effect from the next collision term or step, in every
+ * sampler and precision (the integrand's precision); waits for the work
+ * already queued on the context's stream.  Not part of a checkpoint.
+ * QGBE_EINVAL for a bad row, count, power, coefficient or NULL buffers. */
+qgbe_status qgbe_set_matrix_element(qgbe_ctx* ctx, int32_t row, int32_t n_terms, const double* coef,
+                                    const int32_t* powers);
+
 /* Same with optional diagnostic outputs (extras may be NULL). */
 qgbe_status qgbe_collision_term_ex(qgbe_ctx* ctx, int32_t n_samples, int32_t sampler,
                                    double* A_out, int32_t on_device,

@@ -60,6 +60,8 @@ CollideArgs base_args(qgbe_ctx* c, int n_samples, double* A, double* scale, doub
   a.mass2 = c->d_mass2;
   a.win_lo = 0;
   a.win_n = c->G.nodes;
+  a.msq_mask = c->msq_mask;
+  a.msq = c->d_msq;
   a.A = A;
   a.scale = scale;
   a.items = items;
@@ -369,6 +371,7 @@ qgbe_status qgbe_init_grid(const qgbe_grid_desc* desc, qgbe_ctx** out) {
   ALLOC(c->d_obs_scratch, observables_scratch(c->G), "observables scratch");
   ALLOC(c->d_obs, (size_t)observables_len, "observables");
   ALLOC(c->d_energy, 2, "energy budget");
+  ALLOC(c->d_msq, 1, "matrix element table");
   ALLOC(c->d_mass_part, mass_scratch(c->G), "mass partial sums");
   ALLOC(c->d_count, 1, "accepted counter");
   ALLOC(c->d_mc, 2, "error accumulators");
@@ -424,6 +427,7 @@ void qgbe_destroy(qgbe_ctx* c) {
   (void)hipFree(c->d_lag);
   (void)hipFree(c->d_obs_scratch);
   (void)hipFree(c->d_energy);
+  (void)hipFree(c->d_msq);
   (void)hipFree(c->d_mass_part);
   (void)hipFree(c->d_obs);
   (void)hipFree(c->d_count);
@@ -550,6 +554,31 @@ qgbe_status qgbe_collision_term_ex(qgbe_ctx* c, int32_t n_samples, int32_t sampl
     st->t_collide_ms = ms;
     st->n_evals = (double)c->G.cells * c->nch * c->G.nodes * n_samples;
   }
+  return QGBE_OK;
+}
+
+qgbe_status qgbe_set_matrix_element(qgbe_ctx* c, int32_t row, int32_t n_terms, const double* coef,
+                                    const int32_t* powers) {
+  if (!c) return fail(QGBE_EINVAL, "NULL context");
+  if (row < 1 || row > 7) return fail(QGBE_EINVAL, "row must be 1..7");
+  if (n_terms < 0 || n_terms > kMsqMaxTerms) return fail(QGBE_EINVAL, "0..8 terms per row");
+  if (n_terms > 0 && (!coef || !powers)) return fail(QGBE_EINVAL, "NULL terms");
+  for (int k = 0; k < n_terms; ++k) {
+    if (!std::isfinite(coef[k])) return fail(QGBE_EINVAL, "non-finite coefficient");
+    for (int i = 0; i < 6; ++i)
+      if (powers[6 * k + i] < 0 || powers[6 * k + i] > kMsqMaxPower) return fail(QGBE_EINVAL, "powers must be 0..4");
+  }
+  HIP_TRY(hipSetDevice(c->d.device), "hipSetDevice");
+  c->msq.n[row] = n_terms;
+  for (int k = 0; k < kMsqMaxTerms; ++k) {
+    c->msq.c[row][k] = k < n_terms ? coef[k] : 0.0;
+    for (int i = 0; i < 6; ++i) c->msq.p[row][k][i] = (int8_t)(k < n_terms ? powers[6 * k + i] : 0);
+  }
+  if (n_terms > 0) c->msq_mask |= 1u << row;
+  else c->msq_mask &= ~(1u << row);
+  // the table is read by kernels already queued on the stream: wait for them
+  HIP_TRY(hipStreamSynchronize(c->stream), "synchronise");
+  HIP_TRY(hipMemcpy(c->d_msq, &c->msq, sizeof(MsqTable), hipMemcpyHostToDevice), "copy matrix elements");
   return QGBE_OK;
 }
 

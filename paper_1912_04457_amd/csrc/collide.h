@@ -34,6 +34,8 @@ struct CollideArgs {
   double* mc_acc;         // [2] (may be NULL): sum over items of the variance estimate of their
                           // direct sum, and of the squared direct sums
   double* chan_var;       // [channels] (may be NULL): the variance sum per channel
+  uint32_t msq_mask;      // bit r: Table I row r replaced by the user terms in msq
+  const MsqTable* msq;    // device copy of the user terms (NULL when msq_mask is 0)
   int learned;            // draw from the mixture table instead of uniformly
   int mix_K;              // mixture components
   const uint32_t* mix_thr;   // [channels*nodes][K]

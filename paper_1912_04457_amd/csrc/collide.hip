@@ -168,6 +168,23 @@ __device__ __forceinline__ R matrix_element(int row, R s, R t, R u, R mu) {
   }
 }
 
+// |M|^2 / g^4 of a row: the user's terms where the row was replaced (the
+// row is uniform over a wavefront), else Table I.
+template <typename R>
+__device__ __forceinline__ R msq_row(uint32_t mask, const MsqTable* tab, int row, R s, R t, R u, R mu) {
+  if (!((mask >> row) & 1u)) return matrix_element<R>(row, s, t, u, mu);
+  const R x[6] = {s, t, u, rcp_r<R>(t - mu), rcp_r<R>(u - mu), rcp_r<R>(s)};
+  R sum = R(0);
+  const int n = tab->n[row];
+  for (int k = 0; k < n; ++k) {
+    R term = (R)tab->c[row][k];
+    for (int i = 0; i < 6; ++i)
+      for (int e = 0; e < tab->p[row][k][i]; ++e) term *= x[i];
+    sum += term;
+  }
+  return sum;
+}
+
 // Trilinear stencil over the 8 surrounding cell centres, clamped at the box.
 template <typename R>
 struct Stencil {
@@ -541,8 +558,8 @@ __device__ __forceinline__ R prefactor(const Item& it, const Geo& g) {
 }
 
 template <typename R>
-__device__ __forceinline__ R weight_no_bracket(const Item& it, const Geo& g, int row) {
-  const R m = matrix_element<R>(row, (R)g.s, (R)g.t, (R)g.u, (R)it.mu);
+__device__ __forceinline__ R weight_no_bracket(const CollideArgs& A, const Item& it, const Geo& g, int row) {
+  const R m = msq_row<R>(A.msq_mask, A.msq, row, (R)g.s, (R)g.t, (R)g.u, (R)it.mu);
   return m * prefactor<R>(it, g);
 }
 
@@ -651,7 +668,7 @@ __global__ __launch_bounds__(256) void collide_f64_kernel(CollideArgs A) {
       Geo g;
       if (!geometry(it, G, u, g)) continue;
       ++n_ok;
-      const double wnb = weight_no_bracket<double>(it, g, ch.row) * inv_q;
+      const double wnb = weight_no_bracket<double>(A, it, g, ch.row) * inv_q;
       const Stencil<double> s2 = make_stencil<double>(g.p2, G);
       const Stencil<double> s3 = make_stencil<double>(g.p3, G);
       const Stencil<double> s4 = make_stencil<double>(g.p4, G);
@@ -831,7 +848,8 @@ __global__ __launch_bounds__(256) void collide_roots_kernel(CollideArgs A) {
         const double ms = E12 * E12 - (Pq[0] * Pq[0] + Pq[1] * Pq[1] + Pq[2] * Pq[2]);
         const double mt = E13 * E13 - (d13[0] * d13[0] + d13[1] * d13[1] + d13[2] * d13[2]);
         const double mu = E14 * E14 - (d14[0] * d14[0] + d14[1] * d14[1] + d14[2] * d14[2]);
-        const double wnb = coef * matrix_element<double>(ch.row, ms, mt, mu, it.mu) * rcp64(E2 * E3 * E4 * J);
+        const double wnb = coef * msq_row<double>(A.msq_mask, A.msq, ch.row, ms, mt, mu, it.mu) *
+                           rcp64(E2 * E3 * E4 * J);
         const Stencil<double> s2 = make_stencil<double>(p2, G);
         const Stencil<double> s3 = make_stencil<double>(p3, G);
         const Stencil<double> s4 = make_stencil<double>(p4, G);
@@ -1075,7 +1093,7 @@ __global__ __launch_bounds__(f32_block(kLearned, kQueue)) void collide_f32_kerne
     auto evaluate = [&](const double u[5], float inv_q) {
       Geo g;
       if (!geometry(it, G, u, g)) return;
-      finish(g, weight_no_bracket<float>(it, g, ch.row) * inv_q);
+      finish(g, weight_no_bracket<float>(A, it, g, ch.row) * inv_q);
     };
     if (kQueue) {
       // queued record -> the accepted sample's geometry, as geometry() left it
@@ -1088,8 +1106,8 @@ __global__ __launch_bounds__(f32_block(kLearned, kQueue)) void collide_f32_kerne
           g.p3[a] = q_p3[wid][a][slot];
           g.p4[a] = (it.p1[a] + g.p2[a]) - g.p3[a];
         }
-        const float m = matrix_element<float>(ch.row, q_f[wid][0][slot], q_f[wid][1][slot], q_f[wid][2][slot],
-                                              (float)it.mu);
+        const float m = msq_row<float>(A.msq_mask, A.msq, ch.row, q_f[wid][0][slot], q_f[wid][1][slot],
+                                       q_f[wid][2][slot], (float)it.mu);
         finish(g, m * q_f[wid][3][slot]);
       };
       unsigned head = 0, tail = 0;  // ring positions (wave-uniform)
@@ -1235,7 +1253,7 @@ __global__ __launch_bounds__(256) void record_kernel(CollideArgs A, int n_per_it
     double v = 0.0;
     Geo g;
     if (it.E1 > 0.0 && geometry(it, G, u, g)) {
-      const double wnb = weight_no_bracket<double>(it, g, ch.row);
+      const double wnb = weight_no_bracket<double>(A, it, g, ch.row);
       const Stencil<double> s2 = make_stencil<double>(g.p2, G);
       const Stencil<double> s3 = make_stencil<double>(g.p3, G);
       const Stencil<double> s4 = make_stencil<double>(g.p4, G);

@@ -73,6 +73,9 @@ struct qgbe_ctx {
   double* d_A = nullptr;
   double* d_obs_scratch = nullptr;
   double* d_energy = nullptr;  // [E_source, E_collide] of the last step
+  qgbe::MsqTable msq{};          // user matrix elements (host copy)
+  uint32_t msq_mask = 0;         // rows replaced by them
+  qgbe::MsqTable* d_msq = nullptr;  // device copy
   double* d_mass_part = nullptr;  // per (cell, chunk, species) partial mass integrals
   double* d_obs = nullptr;
   unsigned long long* d_count = nullptr;

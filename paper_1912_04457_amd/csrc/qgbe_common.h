@@ -30,6 +30,16 @@ struct Channel {
   int pos_slot[3];  // slot of positions 2, 3, 4
 };
 
+// User matrix elements: row r (1..7) of Table I replaced by
+// sum_k c_k s^a t^b u^c / ((t - mu)^d (u - mu)^e s^f), in units of g^4.
+constexpr int kMsqMaxTerms = 8;
+constexpr int kMsqMaxPower = 4;
+struct MsqTable {
+  int n[8];                        // terms per row (index 1..7)
+  double c[8][kMsqMaxTerms];
+  int8_t p[8][kMsqMaxTerms][6];    // a, b, c, d, e, f
+};
+
 // Geometry of the phase-space grid, passed by value to every kernel.
 struct Grid {
   int nx[3], np[3];

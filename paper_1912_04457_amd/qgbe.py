@@ -32,7 +32,7 @@ EXPORTS = (
     "qgbe_proposal_get_weights", "qgbe_mlp_forward", "qgbe_mlp_loss_grad", "qgbe_proposal_features",
     "qgbe_record_samples", "qgbe_train_proposal", "qgbe_proposal_build_table", "qgbe_get_proposal_table",
     "qgbe_checkpoint", "qgbe_restore", "qgbe_set_channel_samplers", "qgbe_get_channel_samplers",
-    "qgbe_proposal_judge",
+    "qgbe_proposal_judge", "qgbe_set_matrix_element",
 )
 MLP_PARAMS = 29016
 MLP_BATCH = 16384
@@ -129,6 +129,7 @@ def lib() -> C.CDLL:
             "qgbe_set_channel_samplers": (i32, [p, p]),
             "qgbe_get_channel_samplers": (i32, [p, p]),
             "qgbe_proposal_judge": (i32, [p, i32, i32, p, p]),
+            "qgbe_set_matrix_element": (i32, [p, i32, i32, p, p]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -355,6 +356,14 @@ def qgbe_get_channel_samplers(ctx, n_channels: int) -> np.ndarray:
     return v
 
 
+def qgbe_set_matrix_element(ctx, row: int, terms) -> None:
+    """terms = [(coef, (a, b, c, d, e, f)), ...] (see include/qgbe.h); [] restores Table I."""
+    coef = np.ascontiguousarray([t[0] for t in terms], dtype=np.float64)
+    powers = np.ascontiguousarray([t[1] for t in terms], dtype=np.int32).reshape(-1, 6)
+    _check(lib().qgbe_set_matrix_element(ctx, row, len(terms), coef.ctypes.data_as(C.c_void_p),
+                                         powers.ctypes.data_as(C.c_void_p)))
+
+
 def qgbe_proposal_judge(ctx, n_pilot: int, n_reps: int, n_channels: int):
     """Run the fallback judge; returns (use_learned [channels] uint8, ratio [channels])."""
     flags = np.zeros(n_channels, dtype=np.uint8)
@@ -438,6 +447,11 @@ class Solver:
         st = Stats()
         qgbe_collision_term_ex(self.ctx, n_samples, sampler, A, S, I, st)
         return A, S, I, st
+
+    def observables(self) -> dict:
+        st = Stats()
+        qgbe_observables(self.ctx, st)
+        return st.as_dict()
 
     def step(self, dt_fm: float, n_samples: int, n_steps: int = 1, sampler: int = SAMPLER_UNIFORM):
         stats = (Stats * n_steps)()

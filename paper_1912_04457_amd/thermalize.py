@@ -48,19 +48,27 @@ def soft_nodes(n_p, p_half, k: int = 8) -> np.ndarray:
     return np.argsort((P ** 2).sum(1), kind="stable")[:k]
 
 
-def run(kind: str = "gluon", n_p=(20, 20, 20), p_half=(2.0, 2.0, 2.0), f0: float = 0.5, Qs: float = 1.5,
-        xi: float = 1.0, alpha_s: float = 0.3, dt_fm: float = 0.005, steps: int = 1000, every: int = 100,
-        samples: int = 256, precision: int = qgbe.FP32, seed: int = W.PHILOX_SEED, device: int = 0):
-    """Evolve and return the list of records (dicts)."""
+def evolve(kind: str = "gluon", n_p=(20, 20, 20), p_half=(2.0, 2.0, 2.0), f0: float = 0.5, Qs: float = 1.5,
+           xi: float = 1.0, alpha_s: float = 0.3, dt_fm: float = 0.005, steps: int = 1000, every: int = 100,
+           samples: int = 256, precision: int = qgbe.FP32, seed: int = W.PHILOX_SEED, device: int = 0,
+           const_mass2=None):
+    """Evolve, yielding a record (dict) every ``every`` steps as it is taken.
+    const_mass2: None for the dynamic masses of Eq. mg / mq, else the 7
+    constant squared masses (GeV^2) of the energy test of Sec. IV."""
     if steps < 1 or every < 1:
         raise ValueError("steps and every must be >= 1")
     mask = KINDS[kind]
     f = initial_step(n_p, p_half, mask, f0, Qs, xi)
     soft = soft_nodes(n_p, p_half)
-    records = []
+    masses = {} if const_mass2 is None else dict(mass_mode=qgbe.MASS_CONSTANT, const_mass2=tuple(const_mass2))
     with qgbe.Solver(n_x=(1, 1, 1), n_p=tuple(n_p), p_half=tuple(p_half), species_mask=mask, alpha_s=alpha_s,
-                     precision=precision, seed=seed, device=device) as s:
+                     precision=precision, seed=seed, device=device, **masses) as s:
         s.set_f(f)
+        if every > 0:
+            st0 = s.observables()
+            yield dict(step=0, t_fm=0.0, N_total=st0["N_total"], E_total=st0["E_total"],
+                       E_total_mod=st0["E_total_mod"], entropy=st0["entropy"],
+                       Tzz_over_Txx=st0["T_ii"][2] / st0["T_ii"][0] if st0["T_ii"][0] else None)
         done = 0
         while done < steps:
             k = min(every, steps - done)
@@ -68,13 +76,17 @@ def run(kind: str = "gluon", n_p=(20, 20, 20), p_half=(2.0, 2.0, 2.0), f0: float
             done += k
             fs = s.get_f()[:, 0, soft]
             T = st["T_ii"]
-            records.append(dict(
+            yield dict(
                 step=done, t_fm=done * dt_fm, N_total=st["N_total"], E_total=st["E_total"],
                 E_total_mod=st["E_total_mod"], entropy=st["entropy"], Tzz_over_Txx=T[2] / T[0] if T[0] else None,
                 mass2_g=st["mass2_avg"][W.GLUON], mass2_q=st["mass2_avg"][0], E_source=st["E_source"],
                 E_collide=st["E_collide"], min_f=st["min_f"], f_soft_g=float(fs[W.GLUON].mean()),
-                f_soft_q=float(fs[0].mean()), flags=st["flags"], t_step_ms=st["t_step_ms"]))
-    return records
+                f_soft_q=float(fs[0].mean()), flags=st["flags"], t_step_ms=st["t_step_ms"])
+
+
+def run(*args, **kw) -> list:
+    """evolve() collected into a list."""
+    return list(evolve(*args, **kw))
 
 
 def main(argv=None):
@@ -91,9 +103,12 @@ def main(argv=None):
     ap.add_argument("--every", type=int, default=100)
     ap.add_argument("--samples", type=int, default=256, help="samples per (channel, node)")
     ap.add_argument("--fp64", action="store_true")
+    ap.add_argument("--const-mg2", type=float, default=None,
+                    help="constant gluon mass^2 (GeV^2; quarks get a third of it) instead of Eq. mg / mq")
     a = ap.parse_args(argv)
-    for rec in run(a.kind, (a.n,) * 3, (a.p_half,) * 3, a.f0, a.qs, a.xi, a.alpha_s, a.dt, a.steps, a.every,
-                   a.samples, qgbe.FP64 if a.fp64 else qgbe.FP32):
+    cm = None if a.const_mg2 is None else (a.const_mg2 / 3.0,) * 6 + (a.const_mg2,)
+    for rec in evolve(a.kind, (a.n,) * 3, (a.p_half,) * 3, a.f0, a.qs, a.xi, a.alpha_s, a.dt, a.steps, a.every,
+                      a.samples, qgbe.FP64 if a.fp64 else qgbe.FP32, const_mass2=cm):
         print(json.dumps(rec), flush=True)
 
 

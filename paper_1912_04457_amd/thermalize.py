@@ -64,24 +64,23 @@ def evolve(kind: str = "gluon", n_p=(20, 20, 20), p_half=(2.0, 2.0, 2.0), f0: fl
     with qgbe.Solver(n_x=(1, 1, 1), n_p=tuple(n_p), p_half=tuple(p_half), species_mask=mask, alpha_s=alpha_s,
                      precision=precision, seed=seed, device=device, **masses) as s:
         s.set_f(f)
-        if every > 0:
-            st0 = s.observables()
-            yield dict(step=0, t_fm=0.0, N_total=st0["N_total"], E_total=st0["E_total"],
-                       E_total_mod=st0["E_total_mod"], entropy=st0["entropy"],
-                       Tzz_over_Txx=st0["T_ii"][2] / st0["T_ii"][0] if st0["T_ii"][0] else None)
-        done = 0
-        while done < steps:
-            k = min(every, steps - done)
-            st = s.step(dt_fm, samples, n_steps=k)[-1]
-            done += k
+        def record(done, st):
             fs = s.get_f()[:, 0, soft]
             T = st["T_ii"]
-            yield dict(
+            return dict(
                 step=done, t_fm=done * dt_fm, N_total=st["N_total"], E_total=st["E_total"],
                 E_total_mod=st["E_total_mod"], entropy=st["entropy"], Tzz_over_Txx=T[2] / T[0] if T[0] else None,
                 mass2_g=st["mass2_avg"][W.GLUON], mass2_q=st["mass2_avg"][0], E_source=st["E_source"],
                 E_collide=st["E_collide"], min_f=st["min_f"], f_soft_g=float(fs[W.GLUON].mean()),
                 f_soft_q=float(fs[0].mean()), flags=st["flags"], t_step_ms=st["t_step_ms"])
+
+        yield record(0, s.observables())   # the initial state (masses with E = |p|)
+        done = 0
+        while done < steps:
+            k = min(every, steps - done)
+            st = s.step(dt_fm, samples, n_steps=k)[-1]
+            done += k
+            yield record(done, st)
 
 
 def run(*args, **kw) -> list:

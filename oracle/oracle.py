@@ -97,6 +97,9 @@ def lib():
         _lib.ref_item_sums.argtypes = [p, p, p, u64, u32, i32, i32, C.c_int64, p, p, p, i32]
         _lib.ref_set_matrix_element.restype = i32
         _lib.ref_set_matrix_element.argtypes = [i32, i32, p, p]
+        _lib.ref_item_sums_learned.restype = i32
+        _lib.ref_item_sums_learned.argtypes = [p, p, p, u64, u32, i32, i32, p, p, p, i32, p, C.c_int64, p, p, p,
+                                               i32]
         _lib.ref_item_sums_est.restype = i32
         _lib.ref_item_sums_est.argtypes = [p, p, p, u64, u32, i32, i32, i32, C.c_int64, p, p, p, i32]
         _lib.ref_collision_points.restype = i32
@@ -294,6 +297,35 @@ def collision_learned(grid: Grid, f, mass2, seed: int, step: int, n_samples: int
     if r < 0:
         raise ValueError("oracle rejected the arguments")
     return A, S, items
+
+
+def item_sums_learned(grid: Grid, f, mass2, seed: int, step: int, n_samples: int, thr, mu, sigma, items, *,
+                      table_per_cell: bool = False, chan_learned=None, threads: int = 0,
+                      want_scale: bool = False):
+    """Direct sums of selected (cell, channel, node) items with the mixture
+    proposal (the table as in collision_learned); with want_scale also the
+    sum of the samples' gain+loss magnitudes."""
+    f = _field(grid, f)
+    mass2 = _mass(grid, mass2)
+    thr = np.ascontiguousarray(thr, dtype=np.uint32)
+    mu = np.ascontiguousarray(mu, dtype=np.float32)
+    sigma = np.ascontiguousarray(sigma, dtype=np.float32)
+    K = thr.shape[-1]
+    nch = len(channels(grid))
+    rows = (grid.cells if table_per_cell else 1) * nch * grid.nodes
+    if thr.size != rows * K or mu.size != rows * K * 5 or sigma.size != rows * K * 5:
+        raise ValueError("table shape does not match the grid")
+    if chan_learned is not None:
+        chan_learned = np.ascontiguousarray(chan_learned, dtype=np.uint8)
+    items = np.ascontiguousarray(items, dtype=np.int64).reshape(-1, 3)
+    out = np.zeros(len(items))
+    scale = np.zeros(len(items)) if want_scale else None
+    g = grid.c()
+    if lib().ref_item_sums_learned(C.byref(g), _ptr(f), _ptr(mass2), seed, step, n_samples, K, _ptr(thr),
+                                   _ptr(mu), _ptr(sigma), int(table_per_cell), _ptr(chan_learned),
+                                   len(items), _ptr(items), _ptr(out), _ptr(scale), threads) < 0:
+        raise ValueError("oracle rejected the arguments")
+    return (out, scale) if want_scale else out
 
 
 def item_sums(grid: Grid, f, mass2, seed: int, step: int, n_samples: int, items, *,

@@ -694,12 +694,12 @@ static double log_q_mixture(int K, const uint32_t* thr, const float* mu, const f
 static void run_item_learned(const ref_grid* g, const ref_channel* ch, const double* f,
                              const double* mass2, uint64_t seed, uint32_t step, int32_t N,
                              int K, const uint32_t* thr, const float* mu, const float* sg,
-                             int64_t cell, int64_t p1_lin, accum* acc, double* item) {
+                             int64_t cell, int64_t p1_lin, accum* acc, double* item, double* item_scale) {
   double p1[3];
   node_momentum(g, p1_lin, p1);
   const double V5 = box_volume(g) * 4.0 * PI;
   const double alpha = (double)thr[0] / 4294967296.0;
-  double sum = 0.0;
+  double sum = 0.0, ssum = 0.0;
   for (int32_t s = 0; s < N; ++s) {
     uint32_t x[8];
     draw_block(seed, step, (uint32_t)s, (uint32_t)p1_lin, (uint32_t)cell, (uint32_t)ch->code, 0u, x);
@@ -738,8 +738,10 @@ static void run_item_learned(const ref_grid* g, const ref_channel* ch, const dou
     const double v = ch->w * V5 * pt.g / (N * q), vs = ch->w * V5 * pt.gscale / (N * q);
     deposit_sample(g, ch, acc, cell, p1_lin, (const double(*)[4])pt.k, 1, v, vs, 0.0, 0.0);
     sum += v;
+    ssum += fabs(vs);
   }
   if (item) *item = sum;
+  if (item_scale) *item_scale = ssum;
 }
 
 static int check_grid(const ref_grid* g) {
@@ -805,7 +807,7 @@ static int32_t run_all(const run_args* ra, item_kind kind, double* A_out, double
       const int64_t row = ((ra->table_per_cell ? cell : 0) * nch + ci) * nn + p1;
       run_item_learned(g, &chans[ci], ra->f, ra->mass2, ra->seed, ra->step, ra->N, ra->K,
                        ra->thr + row * ra->K, ra->mu + row * ra->K * 5, ra->sg + row * ra->K * 5,
-                       cell, p1, &acc, item);
+                       cell, p1, &acc, item, NULL);
     }
   }
   for (int t = 0; t < nt; ++t) {
@@ -817,6 +819,47 @@ static int32_t run_all(const run_args* ra, item_kind kind, double* A_out, double
   free(bufA);
   free(bufS);
   return nch;
+}
+
+/* direct sums of selected work items with the mixture proposal (the same
+   table layout and fallback flags as ref_collision_learned) */
+int32_t ref_item_sums_learned(const ref_grid* g, const double* f, const double* mass2, uint64_t seed,
+                              uint32_t step, int32_t n_samples, int32_t K, const uint32_t* thr,
+                              const float* mu, const float* sigma, int32_t table_per_cell,
+                              const uint8_t* chan_learned, int64_t n_sel, const int64_t* items,
+                              double* out, double* out_scale, int32_t n_threads) {
+  if (check_grid(g) || n_samples <= 0 || K < 1 || K > 64) return -1;
+  ref_channel chans[128];
+  const int nch = ref_channels(g, chans, 128);
+  if (nch < 0) return -1;
+  const int64_t nc = n_cells(g), nn = n_nodes(g);
+  for (int64_t i = 0; i < n_sel; ++i)
+    if (items[3 * i] < 0 || items[3 * i] >= nc || items[3 * i + 1] < 0 || items[3 * i + 1] >= nch ||
+        items[3 * i + 2] < 0 || items[3 * i + 2] >= nn)
+      return -1;
+  int nt = 1;
+#ifdef _OPENMP
+  nt = n_threads > 0 ? n_threads : omp_get_max_threads();
+#else
+  (void)n_threads;
+#endif
+#ifdef _OPENMP
+#pragma omp parallel for num_threads(nt) schedule(dynamic)
+#endif
+  for (int64_t i = 0; i < n_sel; ++i) {
+    accum acc = {NULL, NULL};
+    const int64_t cell = items[3 * i], p1 = items[3 * i + 2];
+    const int ci = (int)items[3 * i + 1];
+    if (chan_learned && !chan_learned[ci]) {
+      run_item_uniform(g, &chans[ci], f, mass2, seed, step, n_samples, REF_EST_CM, 1, 0, NULL, cell, p1,
+                       &acc, &out[i], out_scale ? &out_scale[i] : NULL);
+    } else {
+      const int64_t row = ((table_per_cell ? cell : 0) * nch + ci) * nn + p1;
+      run_item_learned(g, &chans[ci], f, mass2, seed, step, n_samples, K, thr + row * K, mu + row * K * 5,
+                       sigma + row * K * 5, cell, p1, &acc, &out[i], out_scale ? &out_scale[i] : NULL);
+    }
+  }
+  return 0;
 }
 
 /* direct sums of selected work items (cell, channel ordinal, node), without

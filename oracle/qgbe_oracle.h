@@ -136,6 +136,13 @@ int32_t ref_collision(const ref_grid* g, const double* f, const double* mass2,
 int32_t ref_item_sums(const ref_grid* g, const double* f, const double* mass2, uint64_t seed,
                       uint32_t step, int32_t n_samples, int32_t symmetric, int64_t n_sel,
                       const int64_t* items, double* out, double* out_scale, int32_t n_threads);
+/* direct sums of selected items with the mixture proposal (table and flags
+   as in ref_collision_learned) */
+int32_t ref_item_sums_learned(const ref_grid* g, const double* f, const double* mass2, uint64_t seed,
+                              uint32_t step, int32_t n_samples, int32_t K, const uint32_t* thr,
+                              const float* mu, const float* sigma, int32_t table_per_cell,
+                              const uint8_t* chan_learned, int64_t n_sel, const int64_t* items,
+                              double* out, double* out_scale, int32_t n_threads);
 /* the same for any estimator of the uniform sampler */
 int32_t ref_item_sums_est(const ref_grid* g, const double* f, const double* mass2, uint64_t seed,
                           uint32_t step, int32_t n_samples, int32_t estimator, int32_t symmetric,

@@ -118,6 +118,7 @@ void make_grid(const qgbe_grid_desc* d, Grid& G) {
     G.dx[a] = 2.0 * d->x_half[a] / d->n_x[a];
     G.dp[a] = 2.0 * d->p_half[a] / d->n_p[a];
     G.inv_dp[a] = 1.0 / G.dp[a];
+    G.pc[a] = G.ph[a] * G.inv_dp[a] - 0.5;
     G.cells *= d->n_x[a];
     G.nodes *= d->n_p[a];
   }

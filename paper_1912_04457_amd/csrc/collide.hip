@@ -195,8 +195,8 @@ struct Stencil {
 // The grid coordinate and its fraction are formed in FP64 so the weights carry
 // a relative (not an absolute 2^-24 * n) error when rounded to R.
 template <typename R>
-__device__ __forceinline__ R clamp_axis(double p, double ph, double inv_dp, int n, int& i0) {
-  const double t = fmin(fmax(fma(p + ph, inv_dp, -0.5), 0.0), (double)(n - 1));
+__device__ __forceinline__ R clamp_axis(double p, double pc, double inv_dp, int n, int& i0) {
+  const double t = fmin(fmax(fma(p, inv_dp, pc), 0.0), (double)(n - 1));
   const int i = min((int)t, n - 2);
   i0 = i;
   return (R)(t - (double)i);
@@ -206,9 +206,9 @@ template <typename R>
 __device__ __forceinline__ Stencil<R> make_stencil(const double p[3], const Grid& G) {
   Stencil<R> st;
   int ix, iy, iz;
-  st.wx = clamp_axis<R>(p[0], G.ph[0], G.inv_dp[0], G.np[0], ix);
-  st.wy = clamp_axis<R>(p[1], G.ph[1], G.inv_dp[1], G.np[1], iy);
-  st.wz = clamp_axis<R>(p[2], G.ph[2], G.inv_dp[2], G.np[2], iz);
+  st.wx = clamp_axis<R>(p[0], G.pc[0], G.inv_dp[0], G.np[0], ix);
+  st.wy = clamp_axis<R>(p[1], G.pc[1], G.inv_dp[1], G.np[1], iy);
+  st.wz = clamp_axis<R>(p[2], G.pc[2], G.inv_dp[2], G.np[2], iz);
   st.base = ix * G.ox + iy * G.oy + iz;
   return st;
 }
@@ -933,14 +933,14 @@ __device__ __forceinline__ Stencil<double> widen(const Stencil<float>& st) {
   return Stencil<double>{st.base, (double)st.wx, (double)st.wy, (double)st.wz};
 }
 
-template <bool kAllLds>
+template <bool kAllLds, bool kWin = true>
 __device__ __forceinline__ void deposit_slot(int k, int slot_lo, int slot_hi, int n_acc, double* acc,
                                              double* __restrict__ out, size_t off, const Stencil<float>& st,
                                              float v, int nodes, int ox, int oy, int win_lo, int win_n) {
   if (k < slot_lo || k >= slot_hi) return;  // deposited by another launch
   const int j = k - slot_lo;
   if (kAllLds || j < n_acc) {
-    if (win_n == nodes)  // (wave-uniform) the whole grid in LDS
+    if (!kWin || win_n == nodes)  // (wave-uniform) the whole grid in LDS
       deposit<double, double, __HIP_MEMORY_SCOPE_WORKGROUP>(acc + j * win_n, widen(st), (double)v, ox, oy);
     else
       deposit_window(acc + j * win_n, widen(st), (double)v, ox, oy, win_lo, win_n);
@@ -1115,13 +1115,13 @@ __global__ __launch_bounds__(f32_block(kLearned, kQueue)) void collide_f32_kerne
         const int s = base + lane;
         uint32_t x0 = (uint32_t)s, x1 = (uint32_t)p1_lin, x2 = (uint32_t)cell, x3 = ((uint32_t)ch.code << 8);
         philox4x32_10(x0, x1, x2, x3, A.key0, A.key1);
-        if (pending) deposit_slot<true>(k2, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off2, pd2, pdv,
+        if (pending) deposit_slot<true, false>(k2, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off2, pd2, pdv,
                                         nodes, G.ox, G.oy, win_lo, win_n);
         double u[5];
         five_uniforms(x0, x1, x2, x3, u);
         Geo g;
         const bool ok = s < A.n_samples && geometry(it, G, u, g);
-        if (pending) deposit_slot<true>(k3, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off3, pd3, -pdv,
+        if (pending) deposit_slot<true, false>(k3, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off3, pd3, -pdv,
                                         nodes, G.ox, G.oy, win_lo, win_n);
         const unsigned long long mask = __ballot(ok);
         if (ok) {
@@ -1135,7 +1135,7 @@ __global__ __launch_bounds__(f32_block(kLearned, kQueue)) void collide_f32_kerne
           q_f[wid][2][slot] = (float)g.u;
           q_f[wid][3][slot] = prefactor<float>(it, g);
         }
-        if (pending) deposit_slot<true>(k4, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off4, pd4, -pdv,
+        if (pending) deposit_slot<true, false>(k4, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off4, pd4, -pdv,
                                         nodes, G.ox, G.oy, win_lo, win_n);
         pending = false;
         tail += (unsigned)__popcll(mask);
@@ -1149,11 +1149,11 @@ __global__ __launch_bounds__(f32_block(kLearned, kQueue)) void collide_f32_kerne
         }
       }
       auto flush = [&]() {
-        deposit_slot<true>(k2, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off2, pd2, pdv,
+        deposit_slot<true, false>(k2, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off2, pd2, pdv,
                            nodes, G.ox, G.oy, win_lo, win_n);
-        deposit_slot<true>(k3, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off3, pd3, -pdv,
+        deposit_slot<true, false>(k3, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off3, pd3, -pdv,
                            nodes, G.ox, G.oy, win_lo, win_n);
-        deposit_slot<true>(k4, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off4, pd4, -pdv,
+        deposit_slot<true, false>(k4, A.slot_lo, A.slot_hi, n_acc, acc, A.A, off4, pd4, -pdv,
                            nodes, G.ox, G.oy, win_lo, win_n);
       };
       if (pending) flush();  // the last full batch

@@ -48,6 +48,7 @@ struct Grid {
   double xh[3], ph[3];     // half-widths
   double dx[3], dp[3];     // cell sizes
   double inv_dp[3];
+  double pc[3];            // ph / dp - 1/2: grid coordinate t = p / dp + pc
   double Vp;               // momentum box volume
   double g2, g4;           // g^2 = 4 pi alpha_s
   uint32_t species_mask;

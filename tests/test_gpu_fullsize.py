@@ -76,3 +76,58 @@ def test_full_size_steps_conserve_number():
     N = np.array([st["N_total"] for st in stats])
     assert np.abs(N - N[0]).max() <= 1e-12 * N[0]
     assert all(st["flags"] & qgbe.FLAG_NONFINITE == 0 for st in stats)
+
+
+def _device_items(torch, s, wl, n_samples, sampler):
+    """One collision term with A, scale and item sums in device memory."""
+    A = torch.zeros((7, wl.cells, wl.nodes), dtype=torch.float64, device="cuda")
+    S = torch.zeros_like(A)
+    I = torch.zeros((wl.cells, s.n_channels, wl.nodes), dtype=torch.float64, device="cuda")
+    qgbe.qgbe_collision_term_ex(s.ctx, n_samples, sampler, A, S, I)
+    torch.cuda.synchronize()
+    return A, S, I
+
+
+@pytest.mark.parametrize("wl", [W.C4.scaled(n_samples=256), W.C5], ids=lambda w: w.name)
+def test_full_size_learned_items(O, wl):
+    """The learned sampler at the benchmark sizes: the 7-species cell with the
+    network's table (re-evaluated on the masses) and a few channels set back to
+    the uniform sampler, and the 12^3-cell spatial grid with an installed
+    table; a seeded sample of 256 work items recomputed by the oracle with the
+    table the kernel used, and per-cell conservation on the whole output."""
+    torch = pytest.importorskip("torch")
+    _case(f"full size learned {wl.name} N={wl.n_samples}")
+    f = W.initial_f(wl)
+    g = O.Grid(n_x=wl.n_x, n_p=wl.n_p, x_half=wl.x_half, p_half=wl.p_half,
+               species_mask=wl.species_mask, alpha_s=wl.alpha_s)
+    nch = len(O.channels(g))
+    rows = nch * wl.nodes
+    flags = None
+    with _solver(wl) as s:
+        s.set_f(f)
+        qgbe.qgbe_set_step_index(s.ctx, 3)
+        if wl.n_x == W.C4.n_x:
+            qgbe.qgbe_proposal_set_weights(s.ctx, W.random_mlp_params(61, head_scale=1.0))
+            qgbe.qgbe_proposal_build_table(s.ctx, 0.1)
+            flags = (np.arange(nch) % 5 != 0).astype(np.uint8)
+            qgbe.qgbe_set_channel_samplers(s.ctx, flags)
+        else:
+            thr, mu, sg = W.random_mog_table(62, rows, K=8, alpha=0.1, mu_scale=1.0, log_sigma=(-1.0, 0.5))
+            qgbe.qgbe_set_proposal_table(s.ctx, thr, mu, sg)
+        A, S, I = _device_items(torch, s, wl, wl.n_samples, qgbe.SAMPLER_LEARNED)
+        thr, mu, sg = qgbe.qgbe_get_proposal_table(s.ctx, rows)   # the table the kernel used
+        m = s.masses()
+        # per-cell conservation over species and nodes, on the device
+        cons = A.sum(dim=(0, 2)).abs() <= 1e-13 * S.sum(dim=(0, 2))
+        assert bool(cons.all())
+        rng = np.random.default_rng(63)
+        items = _sample_items(rng, wl.cells, nch, wl.nodes, 256)
+        inner = np.flatnonzero(np.linalg.norm(W.node_momenta(wl.n_p, wl.p_half), axis=1) < 1.0)
+        items[128:, 2] = rng.choice(inner, 128)
+        idx = torch.from_numpy(items).cuda()
+        got = I[idx[:, 0], idx[:, 1], idx[:, 2]].cpu().numpy()
+    ref, scale = O.item_sums_learned(g, f, m, SEED, 3, wl.n_samples, thr, mu, sg, items, chan_learned=flags,
+                                     want_scale=True)
+    err = np.abs(got - ref)
+    assert np.all(err <= 1e-4 * scale + 1e-300), float((err / np.maximum(scale, 1e-300)).max())
+    assert np.count_nonzero(scale) > 100

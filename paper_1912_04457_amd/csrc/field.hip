@@ -34,16 +34,17 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 // I_Y = sum_p dV/(2pi)^3 f_Y / (2 E_Y) per cell, E_Y from the lagged masses
 // (or |p| when there are none; a node at p = 0 then adds 0).  Stage 1: block
-// (chunk, cell) sums kMassChunk nodes of every species; stage 2: one thread
+// (cell, chunk) sums kMassChunk nodes of every species; stage 2: one thread
 // per cell adds its chunks in order (deterministic) and applies Eq. mg / mq.
 constexpr int kMassChunk = 2048;
 
-int mass_chunks(const Grid& G) { return (G.nodes + kMassChunk - 1) / kMassChunk; }
+__host__ __device__ inline int mass_chunks(const Grid& G) { return (G.nodes + kMassChunk - 1) / kMassChunk; }
 
 __global__ __launch_bounds__(kBlock) void mass_partial(Grid G, const double* __restrict__ f,
                                                        const double* __restrict__ lag, double* part) {
   __shared__ double sh[kBlock / 64];
-  const int chunk = blockIdx.x, cell = blockIdx.y;
+  const int chunks = mass_chunks(G);
+  const int chunk = blockIdx.x % chunks, cell = blockIdx.x / chunks;
   const int lo = chunk * kMassChunk, hi = min(G.nodes, lo + kMassChunk);
   for (int sp = 0; sp < kSpecies; ++sp) {
     const double m2 = lag ? lag[sp * G.cells + cell] : 0.0;
@@ -56,7 +57,7 @@ __global__ __launch_bounds__(kBlock) void mass_partial(Grid G, const double* __r
       if (E > 0.0) acc += fc[node] / (2.0 * E);
     }
     const double t = block_sum(acc, sh);
-    if (threadIdx.x == 0) part[((size_t)cell * gridDim.x + chunk) * kSpecies + sp] = t;
+    if (threadIdx.x == 0) part[((size_t)cell * chunks + chunk) * kSpecies + sp] = t;
   }
 }
 
@@ -344,7 +345,7 @@ size_t mass_scratch(const Grid& G) { return (size_t)G.cells * mass_chunks(G) * k
 hipError_t launch_masses(const Grid& G, const double* f, const double* lag, double* scratch, double* mass2,
                          hipStream_t st) {
   const int chunks = mass_chunks(G);
-  hipLaunchKernelGGL(mass_partial, dim3(chunks, G.cells), dim3(kBlock), 0, st, G, f, lag, scratch);
+  hipLaunchKernelGGL(mass_partial, dim3(chunks * G.cells), dim3(kBlock), 0, st, G, f, lag, scratch);
   hipLaunchKernelGGL(mass_final, dim3((G.cells + kBlock - 1) / kBlock), dim3(kBlock), 0, st, G, scratch, chunks,
                      mass2);
   return hipGetLastError();

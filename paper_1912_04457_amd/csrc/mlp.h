@@ -35,6 +35,9 @@ struct GemmArgs {
   float* Cf;               // activation (FP32) or null
   __bf16* Cb;              // activation (BF16) or null
   long long ldc;
+  int k_chunk;             // > 0: split K into chunks of this many (a multiple of 32), one
+                           // workgroup per (tile, chunk), partial products added into Cf with
+                           // FP32 atomics (Cf zeroed or holding what to add to; no epilogue)
 };
 
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t st);

@@ -35,16 +35,19 @@ __global__ __launch_bounds__(kThreads) void gemm_bf16_kernel(GemmArgs g) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.y * kTile, n0 = blockIdx.x * kTile;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const bool split = g.k_chunk > 0;
+  const int k_begin = split ? blockIdx.z * g.k_chunk : 0;
+  const int k_end = split ? min(g.K, k_begin + g.k_chunk) : g.K;
   floatx4 acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < g.K; k0 += kKStep) {
+  for (int k0 = k_begin; k0 < k_end; k0 += kKStep) {
     // stage the tiles (zero outside the matrices)
     for (int e = tid; e < kTile * kKStep; e += kThreads) {
       const int r = e / kKStep, k = e % kKStep;
       const int gm = m0 + r, gn = n0 + r, gk = k0 + k;
-      As[r][k] = (gm < g.M && gk < g.K) ? g.A[(size_t)gm * g.ars + (size_t)gk * g.acs] : (__bf16)0.0f;
-      Bs[r][k] = (gn < g.N && gk < g.K) ? g.B[(size_t)gk * g.brs + (size_t)gn * g.bcs] : (__bf16)0.0f;
+      As[r][k] = (gm < g.M && gk < k_end) ? g.A[(size_t)gm * g.ars + (size_t)gk * g.acs] : (__bf16)0.0f;
+      Bs[r][k] = (gn < g.N && gk < k_end) ? g.B[(size_t)gk * g.brs + (size_t)gn * g.bcs] : (__bf16)0.0f;
     }
     __syncthreads();
     // operand fragments: lane l holds row (l%16) and k = 8*(l/16) .. +7
@@ -66,6 +69,10 @@ __global__ __launch_bounds__(kThreads) void gemm_bf16_kernel(GemmArgs g) {
       for (int q = 0; q < 4; ++q) {
         const int gm = m0 + wm + i * 16 + rq + q, gn = n0 + wn + j * 16 + c;
         if (gm >= g.M || gn >= g.N) continue;
+        if (split) {  // a partial product over this workgroup's K chunk
+          atomicAdd(&g.Cf[(size_t)gm * g.ldc + gn], acc[i][j][q]);
+          continue;
+        }
         float z = acc[i][j][q];
         if (g.bias) z += g.bias[gn];
         if (g.accumulate) z += g.Cf[(size_t)gm * g.ldc + gn];
@@ -374,7 +381,10 @@ unsigned blocks_for(size_t n, int t = 256) {
 
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
-  dim3 grid((g.N + kTile - 1) / kTile, (g.M + kTile - 1) / kTile);
+  if (g.k_chunk < 0 || g.k_chunk % kKStep) return hipErrorInvalidValue;
+  if (g.k_chunk > 0 && (!g.Cf || g.bias || g.silu || g.Cz || g.Cb)) return hipErrorInvalidValue;
+  const int chunks = g.k_chunk > 0 ? (g.K + g.k_chunk - 1) / g.k_chunk : 1;
+  dim3 grid((g.N + kTile - 1) / kTile, (g.M + kTile - 1) / kTile, chunks);
   hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(kThreads), 0, st, g);
   return hipGetLastError();
 }

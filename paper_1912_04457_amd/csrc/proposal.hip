@@ -76,6 +76,10 @@ qgbe_status forward_staged(qgbe_ctx* c, int rows) {
   return QGBE_OK;
 }
 
+// The weight gradients reduce over the rows (K = rows, M x N <= 128 x 128):
+// their K is split so that rows / 256 workgroups per tile share it.
+constexpr int kGradChunk = 256;
+
 // Loss and gradient for rows staged in m.Xb / m.yw; gradient in m.grad,
 // loss in m.scalars[0] (accumulated).
 qgbe_status loss_grad_staged(qgbe_ctx* c, int rows) {
@@ -88,7 +92,7 @@ qgbe_status loss_grad_staged(qgbe_ctx* c, int rows) {
   HIP_TRY(hipMemsetAsync(m.grad, 0, kMlpParams * sizeof(float), c->stream), "zero grad");
   // layer 3: dW3 = H2^T dY, db3 = colsum dY, dH2 = dY W3^T
   GemmArgs w3 = gemm(kMlpHidden, kMlpOut, rows, m.H2b, 1, kMlpHidden, m.dYb, kMlpOut, 1);
-  w3.Cf = m.grad + kOffW3;
+  w3.Cf = m.grad + kOffW3; w3.k_chunk = kGradChunk;
   HIP_TRY(launch_gemm(w3, c->stream), "dW3");
   HIP_TRY(launch_colsum(m.dY, rows, kMlpOut, m.grad + kOffB3, c->stream), "db3");
   GemmArgs h2 = gemm(rows, kMlpHidden, kMlpOut, m.dYb, kMlpOut, 1, m.pb + kOffW3, 1, kMlpOut);
@@ -97,7 +101,7 @@ qgbe_status loss_grad_staged(qgbe_ctx* c, int rows) {
   HIP_TRY(launch_silu_backward(m.dH, m.Z2, m.dZ, m.dZb, (size_t)rows * kMlpHidden, c->stream), "dZ2");
   // layer 2
   GemmArgs w2 = gemm(kMlpHidden, kMlpHidden, rows, m.H1b, 1, kMlpHidden, m.dZb, kMlpHidden, 1);
-  w2.Cf = m.grad + kOffW2;
+  w2.Cf = m.grad + kOffW2; w2.k_chunk = kGradChunk;
   HIP_TRY(launch_gemm(w2, c->stream), "dW2");
   HIP_TRY(launch_colsum(m.dZ, rows, kMlpHidden, m.grad + kOffB2, c->stream), "db2");
   GemmArgs h1 = gemm(rows, kMlpHidden, kMlpHidden, m.dZb, kMlpHidden, 1, m.pb + kOffW2, 1, kMlpHidden);
@@ -106,7 +110,7 @@ qgbe_status loss_grad_staged(qgbe_ctx* c, int rows) {
   HIP_TRY(launch_silu_backward(m.dH, m.Z1, m.dZ, m.dZb, (size_t)rows * kMlpHidden, c->stream), "dZ1");
   // layer 1
   GemmArgs w1 = gemm(kMlpIn, kMlpHidden, rows, m.Xb, 1, kMlpIn, m.dZb, kMlpHidden, 1);
-  w1.Cf = m.grad + kOffW1;
+  w1.Cf = m.grad + kOffW1; w1.k_chunk = kGradChunk;
   HIP_TRY(launch_gemm(w1, c->stream), "dW1");
   HIP_TRY(launch_colsum(m.dZ, rows, kMlpHidden, m.grad + kOffB1, c->stream), "db1");
   return QGBE_OK;

@@ -170,8 +170,8 @@ void plan_groups(qgbe_ctx* c) {
 // Enqueue the collision kernels accumulating into A (zeroed by the caller).
 qgbe_status run_collide(qgbe_ctx* c, int n_samples, int sampler, double* A, double* scale, double* items) {
   const bool learned = sampler == QGBE_SAMPLER_LEARNED;
-  HIP_TRY(launch_zero_u64(c->d_count, c->stream), "zero counter");
-  HIP_TRY(launch_fill(c->d_mc, 0.0, 2, c->stream), "zero error accumulators");
+  HIP_TRY(launch_zero_u64(c->d_count, kStripes, c->stream), "zero counter");
+  HIP_TRY(launch_fill(c->d_mc, 0.0, 2 * kStripes, c->stream), "zero error accumulators");
   HIP_TRY(launch_fill(c->d_chan_var, 0.0, std::max(1, c->nch), c->stream), "zero channel variances");
   if (c->nch == 0) return QGBE_OK;
   CollideArgs a = base_args(c, n_samples, A, scale, items);
@@ -267,11 +267,10 @@ void fill_stats(qgbe_ctx* c, const double* obs, const double* mass2_host, qgbe_s
 qgbe_status read_stats(qgbe_ctx* c, qgbe_stats* st, bool energy = false) {
   HIP_TRY(launch_observables(c->G, c->d_f, c->d_mass2, c->d_obs_scratch, c->d_obs, c->stream), "observables");
   double obs[observables_len];
-  unsigned long long accepted = 0;
-  HIP_TRY(hipMemcpyAsync(&accepted, c->d_count, sizeof accepted, hipMemcpyDeviceToHost, c->stream),
-          "copy counter");
-  double mc[2] = {0.0, 0.0};
-  HIP_TRY(hipMemcpyAsync(mc, c->d_mc, sizeof mc, hipMemcpyDeviceToHost, c->stream), "copy error accumulators");
+  unsigned long long counts[kStripes];
+  HIP_TRY(hipMemcpyAsync(counts, c->d_count, sizeof counts, hipMemcpyDeviceToHost, c->stream), "copy counter");
+  double mcs[2 * kStripes];
+  HIP_TRY(hipMemcpyAsync(mcs, c->d_mc, sizeof mcs, hipMemcpyDeviceToHost, c->stream), "copy error accumulators");
   std::vector<double> m2((size_t)kSpecies * c->G.cells);
   HIP_TRY(hipMemcpyAsync(obs, c->d_obs, sizeof obs, hipMemcpyDeviceToHost, c->stream), "copy observables");
   HIP_TRY(hipMemcpyAsync(m2.data(), c->d_mass2, m2.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream),
@@ -280,6 +279,13 @@ qgbe_status read_stats(qgbe_ctx* c, qgbe_stats* st, bool energy = false) {
   if (energy)
     HIP_TRY(hipMemcpyAsync(budget, c->d_energy, sizeof budget, hipMemcpyDeviceToHost, c->stream), "copy energy budget");
   HIP_TRY(hipStreamSynchronize(c->stream), "synchronise");
+  unsigned long long accepted = 0;
+  double mc[2] = {0.0, 0.0};
+  for (int i = 0; i < kStripes; ++i) {  // in stripe order: the same sum for the same stripes
+    accepted += counts[i];
+    mc[0] += mcs[2 * i];
+    mc[1] += mcs[2 * i + 1];
+  }
   fill_stats(c, obs, m2.data(), st);
   st->E_source = budget[0];
   st->E_collide = budget[1];
@@ -374,8 +380,8 @@ qgbe_status qgbe_init_grid(const qgbe_grid_desc* desc, qgbe_ctx** out) {
   ALLOC(c->d_energy, 2, "energy budget");
   ALLOC(c->d_msq, 1, "matrix element table");
   ALLOC(c->d_mass_part, mass_scratch(c->G), "mass partial sums");
-  ALLOC(c->d_count, 1, "accepted counter");
-  ALLOC(c->d_mc, 2, "error accumulators");
+  ALLOC(c->d_count, kStripes, "accepted counter");
+  ALLOC(c->d_mc, 2 * kStripes, "error accumulators");
   ALLOC(c->d_chan_var, std::max(1, c->nch), "channel variances");
 #undef ALLOC
   const char* what = "copy channel table";

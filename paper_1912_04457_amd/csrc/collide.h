@@ -5,6 +5,10 @@
 
 namespace qgbe {
 
+// Stripes of the per-launch totals: one global atomic per workgroup lands on
+// one of kStripes addresses, so same-address atomics do not serialise.
+constexpr int kStripes = 64;
+
 struct CollideArgs {
   Grid G;
   const Channel* chans;   // device channel table (all channels)
@@ -30,9 +34,10 @@ struct CollideArgs {
   double* A;              // [7][cells][nodes], accumulated into
   double* scale;          // optional, same shape
   double* items;          // optional [cells][n_channels][nodes]
-  unsigned long long* n_accepted;  // samples above threshold and inside the box
-  double* mc_acc;         // [2] (may be NULL): sum over items of the variance estimate of their
-                          // direct sum, and of the squared direct sums
+  unsigned long long* n_accepted;  // [kStripes]: samples above threshold and inside the box
+  double* mc_acc;         // [kStripes][2] (may be NULL): sum over items of the variance estimate
+                          // of their direct sum, and of the squared direct sums
+                          // (workgroup b adds into stripe b mod kStripes; the reader sums them)
   double* chan_var;       // [channels] (may be NULL): the variance sum per channel
   uint32_t msq_mask;      // bit r: Table I row r replaced by the user terms in msq
   const MsqTable* msq;    // device copy of the user terms (NULL when msq_mask is 0)

@@ -595,11 +595,12 @@ struct BlockTotals {
   }
   __device__ void flush(unsigned long long* g_ok, double* g_mc) {
     __syncthreads();
+    const int stripe = blockIdx.x % kStripes;
     if (threadIdx.x == 0) {
-      if (g_ok) atomicAdd(g_ok, *ok);
+      if (g_ok) atomicAdd(g_ok + stripe, *ok);
       if (g_mc) {
-        atomicAdd(&g_mc[0], mc[0]);
-        atomicAdd(&g_mc[1], mc[1]);
+        atomicAdd(&g_mc[2 * stripe], mc[0]);
+        atomicAdd(&g_mc[2 * stripe + 1], mc[1]);
       }
     }
   }
@@ -1199,8 +1200,9 @@ __global__ __launch_bounds__(f32_block(kLearned, kQueue)) void collide_f32_kerne
     }
   }
   __syncthreads();
-  if (threadIdx.x < 2 && A.mc_acc && A.direct) atomicAdd(&A.mc_acc[threadIdx.x], mc_wg[threadIdx.x]);
-  if (threadIdx.x == 0 && A.n_accepted && A.direct) atomicAdd(A.n_accepted, ok_wg);
+  const int stripe = blockIdx.x % kStripes;
+  if (threadIdx.x < 2 && A.mc_acc && A.direct) atomicAdd(&A.mc_acc[2 * stripe + threadIdx.x], mc_wg[threadIdx.x]);
+  if (threadIdx.x == 0 && A.n_accepted && A.direct) atomicAdd(A.n_accepted + stripe, ok_wg);
   if (threadIdx.x == 0 && A.chan_var && A.direct) atomicAdd(&A.chan_var[ci], mc_wg[0]);  // one channel per workgroup
   if (n_acc > 0) {
     for (int i = threadIdx.x; i < n_acc * win_n; i += blockDim.x) {

@@ -36,6 +36,6 @@ hipError_t launch_to_f32(const double* src, float* dst, size_t n, hipStream_t st
 // loads; entries on the last z or y layer (never a stencil base) repeat f[i].
 hipError_t launch_f32_quads(const Grid& G, const float* f32, float4* q, hipStream_t st);
 hipError_t launch_fill(double* dst, double v, size_t n, hipStream_t st);
-hipError_t launch_zero_u64(unsigned long long* dst, hipStream_t st);
+hipError_t launch_zero_u64(unsigned long long* dst, int n, hipStream_t st);
 
 }  // namespace qgbe

@@ -330,7 +330,10 @@ __global__ void fill_kernel(double* __restrict__ dst, double v, size_t n) {
     dst[i] = v;
 }
 
-__global__ void zero_u64_kernel(unsigned long long* dst) { *dst = 0ull; }
+__global__ void zero_u64_kernel(unsigned long long* dst, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = 0ull;
+}
 
 unsigned grid_for(size_t n) {
   size_t b = (n + kBlock - 1) / kBlock;
@@ -404,8 +407,8 @@ hipError_t launch_fill(double* dst, double v, size_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_zero_u64(unsigned long long* dst, hipStream_t st) {
-  hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, st, dst);
+hipError_t launch_zero_u64(unsigned long long* dst, int n, hipStream_t st) {
+  hipLaunchKernelGGL(zero_u64_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, dst, n);
   return hipGetLastError();
 }
 

@@ -172,7 +172,7 @@ qgbe_status run_collide(qgbe_ctx* c, int n_samples, int sampler, double* A, doub
   const bool learned = sampler == QGBE_SAMPLER_LEARNED;
   HIP_TRY(launch_zero_u64(c->d_count, kStripes, c->stream), "zero counter");
   HIP_TRY(launch_fill(c->d_mc, 0.0, 2 * kStripes, c->stream), "zero error accumulators");
-  HIP_TRY(launch_fill(c->d_chan_var, 0.0, std::max(1, c->nch), c->stream), "zero channel variances");
+  HIP_TRY(launch_fill(c->d_chan_var, 0.0, kStripes * std::max(1, c->nch), c->stream), "zero channel variances");
   if (c->nch == 0) return QGBE_OK;
   CollideArgs a = base_args(c, n_samples, A, scale, items);
   a.learned = learned ? 1 : 0;
@@ -382,7 +382,7 @@ qgbe_status qgbe_init_grid(const qgbe_grid_desc* desc, qgbe_ctx** out) {
   ALLOC(c->d_mass_part, mass_scratch(c->G), "mass partial sums");
   ALLOC(c->d_count, kStripes, "accepted counter");
   ALLOC(c->d_mc, 2 * kStripes, "error accumulators");
-  ALLOC(c->d_chan_var, std::max(1, c->nch), "channel variances");
+  ALLOC(c->d_chan_var, kStripes * std::max(1, c->nch), "channel variances");
 #undef ALLOC
   const char* what = "copy channel table";
   hipError_t e = hipSuccess;

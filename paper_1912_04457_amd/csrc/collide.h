@@ -38,7 +38,7 @@ struct CollideArgs {
   double* mc_acc;         // [kStripes][2] (may be NULL): sum over items of the variance estimate
                           // of their direct sum, and of the squared direct sums
                           // (workgroup b adds into stripe b mod kStripes; the reader sums them)
-  double* chan_var;       // [channels] (may be NULL): the variance sum per channel
+  double* chan_var;       // [kStripes][n_channels] (may be NULL): variance sums per channel, striped
   uint32_t msq_mask;      // bit r: Table I row r replaced by the user terms in msq
   const MsqTable* msq;    // device copy of the user terms (NULL when msq_mask is 0)
   int learned;            // draw from the mixture table instead of uniformly

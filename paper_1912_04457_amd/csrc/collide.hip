@@ -574,35 +574,43 @@ __device__ __forceinline__ double item_variance(double s, double sq, int n) {
 
 }  // namespace
 
-// Per-workgroup totals of the accepted count and the two error sums: the
-// waves add into LDS and one thread adds the workgroup's totals into global
-// memory at the end (one global atomic per workgroup instead of per item).
+// Per-workgroup totals of the accepted count, the two error sums and the
+// per-channel variance sums: the waves add into LDS and the workgroup adds
+// its totals into global memory at the end, into stripe b mod kStripes (one
+// global atomic per workgroup and value instead of one per item on a single
+// address).
 struct BlockTotals {
   unsigned long long* ok;
-  double* mc;  // [2]
+  double* mc;   // [2]
+  double* var;  // [kMaxChannels]
   __device__ void init() {
     if (threadIdx.x == 0) {
       *ok = 0ull;
       mc[0] = 0.0;
       mc[1] = 0.0;
     }
+    for (int i = threadIdx.x; i < kMaxChannels; i += blockDim.x) var[i] = 0.0;
     __syncthreads();
   }
-  __device__ void add(int n_ok, double var, double sq) {
+  __device__ void add(int n_ok, double item_var, double sq, int ci) {
     __hip_atomic_fetch_add(ok, (unsigned long long)n_ok, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    __hip_atomic_fetch_add(&mc[0], var, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(&mc[0], item_var, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     __hip_atomic_fetch_add(&mc[1], sq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_add(&var[ci], item_var, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
-  __device__ void flush(unsigned long long* g_ok, double* g_mc) {
+  __device__ void flush(const CollideArgs& A) {
     __syncthreads();
     const int stripe = blockIdx.x % kStripes;
     if (threadIdx.x == 0) {
-      if (g_ok) atomicAdd(g_ok + stripe, *ok);
-      if (g_mc) {
-        atomicAdd(&g_mc[2 * stripe], mc[0]);
-        atomicAdd(&g_mc[2 * stripe + 1], mc[1]);
+      if (A.n_accepted) atomicAdd(A.n_accepted + stripe, *ok);
+      if (A.mc_acc) {
+        atomicAdd(&A.mc_acc[2 * stripe], mc[0]);
+        atomicAdd(&A.mc_acc[2 * stripe + 1], mc[1]);
       }
     }
+    if (A.chan_var)
+      for (int i = threadIdx.x; i < A.n_channels; i += blockDim.x)
+        if (var[i] != 0.0) atomicAdd(&A.chan_var[(size_t)stripe * A.n_channels + i], var[i]);
   }
 };
 
@@ -615,7 +623,8 @@ __global__ __launch_bounds__(256) void collide_f64_kernel(CollideArgs A) {
   const Grid& G = A.G;
   __shared__ unsigned long long blk_ok;
   __shared__ double blk_mc[2];
-  BlockTotals blk{&blk_ok, blk_mc};
+  __shared__ double blk_var[kMaxChannels];
+  BlockTotals blk{&blk_ok, blk_mc, blk_var};
   blk.init();
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
@@ -698,17 +707,16 @@ __global__ __launch_bounds__(256) void collide_f64_kernel(CollideArgs A) {
     }
     dsum = wave_sum(dsum);
     if (A.scale) ssum = wave_sum(ssum);
-    if (A.mc_acc) dsq = wave_sum(dsq);
+    dsq = wave_sum(dsq);
     const int ok_total = wave_count(n_ok);
     if (lane == 0) {
-      blk.add(ok_total, A.mc_acc ? item_variance(dsum, dsq, A.n_samples) : 0.0, dsum * dsum);
-      if (A.mc_acc && A.chan_var) atomicAdd(&A.chan_var[ci], item_variance(dsum, dsq, A.n_samples));
+      blk.add(ok_total, item_variance(dsum, dsq, A.n_samples), dsum * dsum, ci);
       atomicAdd(Ac[0] + p1_lin, dsum);
       if (A.scale) atomicAdd(Sc[0] + p1_lin, ssum);
       if (A.items) A.items[((size_t)cell * A.n_channels + ci) * G.nodes + p1_lin] = dsum;
     }
   }
-  blk.flush(A.n_accepted, A.mc_acc);
+  blk.flush(A);
 }
 
 // ---------------------------------------------------------------------------
@@ -740,7 +748,8 @@ __global__ __launch_bounds__(256) void collide_roots_kernel(CollideArgs A) {
   const Grid& G = A.G;
   __shared__ unsigned long long blk_ok;
   __shared__ double blk_mc[2];
-  BlockTotals blk{&blk_ok, blk_mc};
+  __shared__ double blk_var[kMaxChannels];
+  BlockTotals blk{&blk_ok, blk_mc, blk_var};
   blk.init();
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
@@ -881,17 +890,16 @@ __global__ __launch_bounds__(256) void collide_roots_kernel(CollideArgs A) {
     }
     dsum = wave_sum(dsum);
     if (A.scale) ssum = wave_sum(ssum);
-    if (A.mc_acc) dsq = wave_sum(dsq);
+    dsq = wave_sum(dsq);
     const int ok_total = wave_count(n_ok);
     if (lane == 0) {
-      blk.add(ok_total, A.mc_acc ? item_variance(dsum, dsq, A.n_samples) : 0.0, dsum * dsum);
-      if (A.mc_acc && A.chan_var) atomicAdd(&A.chan_var[ci], item_variance(dsum, dsq, A.n_samples));
+      blk.add(ok_total, item_variance(dsum, dsq, A.n_samples), dsum * dsum, ci);
       atomicAdd(Ac[0] + p1_lin, dsum);
       if (A.scale) atomicAdd(Sc[0] + p1_lin, ssum);
       if (A.items) A.items[((size_t)cell * A.n_channels + ci) * G.nodes + p1_lin] = dsum;
     }
   }
-  blk.flush(A.n_accepted, A.mc_acc);
+  blk.flush(A);
 }
 
 // ---------------------------------------------------------------------------
@@ -1203,7 +1211,8 @@ __global__ __launch_bounds__(f32_block(kLearned, kQueue)) void collide_f32_kerne
   const int stripe = blockIdx.x % kStripes;
   if (threadIdx.x < 2 && A.mc_acc && A.direct) atomicAdd(&A.mc_acc[2 * stripe + threadIdx.x], mc_wg[threadIdx.x]);
   if (threadIdx.x == 0 && A.n_accepted && A.direct) atomicAdd(A.n_accepted + stripe, ok_wg);
-  if (threadIdx.x == 0 && A.chan_var && A.direct) atomicAdd(&A.chan_var[ci], mc_wg[0]);  // one channel per workgroup
+  if (threadIdx.x == 0 && A.chan_var && A.direct)  // one channel per workgroup
+    atomicAdd(&A.chan_var[(size_t)stripe * A.n_channels + ci], mc_wg[0]);
   if (n_acc > 0) {
     for (int i = threadIdx.x; i < n_acc * win_n; i += blockDim.x) {
       const double v = acc[i];

@@ -80,7 +80,7 @@ struct qgbe_ctx {
   double* d_obs = nullptr;
   unsigned long long* d_count = nullptr;
   double* d_mc = nullptr;          // [2] MC error accumulators of the last collision term
-  double* d_chan_var = nullptr;    // [channels] per-channel variance sums of the last collision term
+  double* d_chan_var = nullptr;    // [kStripes][channels] per-channel variance sums of the last collision term
   uint32_t step = 0;
   int K = 0;                       // proposal table components (0 = none)
   uint32_t* d_thr = nullptr;

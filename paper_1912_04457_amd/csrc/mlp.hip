@@ -124,55 +124,59 @@ __global__ void nll_kernel(const float* __restrict__ Y, const float* __restrict_
                            const double* __restrict__ wsum, float* __restrict__ dY, __bf16* __restrict__ dYb,
                            double* loss) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= rows) return;
-  const float* h = Y + (size_t)r * kMlpOut;
-  const float* yr = yw + (size_t)r * yws;
-  const float s = (float)((double)yr[kMixD] / *wsum);
-  float mx = -INFINITY;
-  for (int k = 0; k < kMixK; ++k) mx = fmaxf(mx, h[k]);
-  float se = 0.f;
-  for (int k = 0; k < kMixK; ++k) se += __expf(h[k] - mx);
-  const float lse_a = mx + __logf(se);
-  float lk[kMixK];
-  float z[kMixK][kMixD];
-  float m2 = -INFINITY;
-  for (int k = 0; k < kMixK; ++k) {
-    float l = h[k] - lse_a;
-    for (int d = 0; d < kMixD; ++d) {
-      const float lr = h[kMixK + kMixK * kMixD + k * kMixD + d];
-      const float ls = fminf(fmaxf(lr, kLsMin), kLsMax);
-      const float zz = (yr[d] - h[kMixK + k * kMixD + d]) * __expf(-ls);
-      z[k][d] = zz;
-      l += -0.5f * zz * zz - ls - 0.91893853320467274f;
+  double part = 0.0;  // this row's loss term; summed over the wave before the atomic
+  if (r < rows) {
+    const float* h = Y + (size_t)r * kMlpOut;
+    const float* yr = yw + (size_t)r * yws;
+    const float s = (float)((double)yr[kMixD] / *wsum);
+    float mx = -INFINITY;
+    for (int k = 0; k < kMixK; ++k) mx = fmaxf(mx, h[k]);
+    float se = 0.f;
+    for (int k = 0; k < kMixK; ++k) se += __expf(h[k] - mx);
+    const float lse_a = mx + __logf(se);
+    float lk[kMixK];
+    float z[kMixK][kMixD];
+    float m2 = -INFINITY;
+    for (int k = 0; k < kMixK; ++k) {
+      float l = h[k] - lse_a;
+      for (int d = 0; d < kMixD; ++d) {
+        const float lr = h[kMixK + kMixK * kMixD + k * kMixD + d];
+        const float ls = fminf(fmaxf(lr, kLsMin), kLsMax);
+        const float zz = (yr[d] - h[kMixK + k * kMixD + d]) * __expf(-ls);
+        z[k][d] = zz;
+        l += -0.5f * zz * zz - ls - 0.91893853320467274f;
+      }
+      lk[k] = l;
+      m2 = fmaxf(m2, l);
     }
-    lk[k] = l;
-    m2 = fmaxf(m2, l);
-  }
-  float se2 = 0.f;
-  for (int k = 0; k < kMixK; ++k) se2 += __expf(lk[k] - m2);
-  const float L = m2 + __logf(se2);
-  atomicAdd(loss, -(double)s * (double)L);
-  float* g = dY + (size_t)r * kMlpOut;
-  __bf16* gb = dYb + (size_t)r * kMlpOut;
-  for (int k = 0; k < kMixK; ++k) {
-    const float resp = __expf(lk[k] - L);
-    const float pi = __expf(h[k] - lse_a);
-    const float ga = -s * (resp - pi);
-    g[k] = ga;
-    gb[k] = (__bf16)ga;
-    for (int d = 0; d < kMixD; ++d) {
-      const float lr = h[kMixK + kMixK * kMixD + k * kMixD + d];
-      const float ls = fminf(fmaxf(lr, kLsMin), kLsMax);
-      const float gmu = -s * resp * z[k][d] * __expf(-ls);
-      float gls = -s * resp * (z[k][d] * z[k][d] - 1.0f);
-      if (lr < kLsMin || lr > kLsMax) gls = 0.f;
-      const int im = kMixK + k * kMixD + d, il = kMixK + kMixK * kMixD + k * kMixD + d;
-      g[im] = gmu;
-      gb[im] = (__bf16)gmu;
-      g[il] = gls;
-      gb[il] = (__bf16)gls;
+    float se2 = 0.f;
+    for (int k = 0; k < kMixK; ++k) se2 += __expf(lk[k] - m2);
+    const float L = m2 + __logf(se2);
+    part = -(double)s * (double)L;
+    float* g = dY + (size_t)r * kMlpOut;
+    __bf16* gb = dYb + (size_t)r * kMlpOut;
+    for (int k = 0; k < kMixK; ++k) {
+      const float resp = __expf(lk[k] - L);
+      const float pi = __expf(h[k] - lse_a);
+      const float ga = -s * (resp - pi);
+      g[k] = ga;
+      gb[k] = (__bf16)ga;
+      for (int d = 0; d < kMixD; ++d) {
+        const float lr = h[kMixK + kMixK * kMixD + k * kMixD + d];
+        const float ls = fminf(fmaxf(lr, kLsMin), kLsMax);
+        const float gmu = -s * resp * z[k][d] * __expf(-ls);
+        float gls = -s * resp * (z[k][d] * z[k][d] - 1.0f);
+        if (lr < kLsMin || lr > kLsMax) gls = 0.f;
+        const int im = kMixK + k * kMixD + d, il = kMixK + kMixK * kMixD + k * kMixD + d;
+        g[im] = gmu;
+        gb[im] = (__bf16)gmu;
+        g[il] = gls;
+        gb[il] = (__bf16)gls;
+      }
     }
   }
+  for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+  if ((threadIdx.x & 63) == 0) atomicAdd(loss, part);
 }
 
 // Adam (bias-corrected) on the FP32 master weights; refresh the BF16 copies.

@@ -364,7 +364,7 @@ qgbe_status qgbe_proposal_judge(qgbe_ctx* c, int32_t n_pilot, int32_t n_reps, ui
   if (!c->K) return fail(QGBE_ESTATE, "no proposal table installed");
   HIP_TRY(hipSetDevice(c->d.device), "hipSetDevice");
   const int nch = std::max(1, c->nch);
-  std::vector<double> var[2], h(nch);
+  std::vector<double> var[2], h((size_t)kStripes * nch);
   double t_ms[2] = {0.0, 0.0};
   const uint32_t saved_step = c->step;
   qgbe_status s = reset_channel_samplers(c);
@@ -377,9 +377,10 @@ qgbe_status qgbe_proposal_judge(qgbe_ctx* c, int32_t n_pilot, int32_t n_reps, ui
       s = qgbe_collision_term_ex(c, n_pilot, l ? QGBE_SAMPLER_LEARNED : QGBE_SAMPLER_UNIFORM, c->d_A, 1, nullptr, &st);
       if (s) break;
       t_ms[l] += st.t_collide_ms;
-      hipError_t e = hipMemcpy(h.data(), c->d_chan_var, nch * sizeof(double), hipMemcpyDeviceToHost);
+      hipError_t e = hipMemcpy(h.data(), c->d_chan_var, h.size() * sizeof(double), hipMemcpyDeviceToHost);
       if (e != hipSuccess) { s = hip_fail(e, "copy channel variances"); break; }
-      for (int ci = 0; ci < nch; ++ci) var[l][ci] += h[ci];
+      for (int k = 0; k < kStripes; ++k)  // the stripes in order
+        for (int ci = 0; ci < nch; ++ci) var[l][ci] += h[(size_t)k * nch + ci];
     }
   }
   c->step = saved_step;

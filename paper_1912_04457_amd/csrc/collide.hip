@@ -625,6 +625,10 @@ __global__ __launch_bounds__(256) void collide_f64_kernel(CollideArgs A) {
   __shared__ double blk_mc[2];
   __shared__ double blk_var[kMaxChannels];
   BlockTotals blk{&blk_ok, blk_mc, blk_var};
+  __shared__ Channel s_ch[kMaxChannels];
+  __shared__ int s_group[kMaxChannels];
+  for (int i = threadIdx.x; i < A.n_group; i += blockDim.x) s_group[i] = A.group[i];
+  for (int i = threadIdx.x; i < A.n_channels; i += blockDim.x) s_ch[i] = A.chans[i];
   blk.init();
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
@@ -634,8 +638,8 @@ __global__ __launch_bounds__(256) void collide_f64_kernel(CollideArgs A) {
     const int p1_lin = (int)(w % G.nodes);
     const int gi = (int)((w / G.nodes) % A.n_group);
     const int cell = (int)(w / ((long long)G.nodes * A.n_group));
-    const int ci = A.group[gi];
-    const Channel ch = A.chans[ci];
+    const int ci = s_group[gi];
+    const Channel ch = s_ch[ci];
     Item it;
     load_item(it, A, ch, cell, p1_lin);
     if (!(it.E1 > 0.0)) {  // massless p = 0 node: zero measure
@@ -740,18 +744,34 @@ __global__ __launch_bounds__(256) void collide_f64_kernel(CollideArgs A) {
 // The value of a root is w V5 / N |M|^2 B / ((2 pi)^5 16 E1 E2 E3 E4 |J|),
 // V5 = (2 P)^3 (2 Px) (2 Py), J the z derivative of the energy sum.  FP64
 // throughout (f from the FP64 field, FP64 atomics): the reference method.
+// Every lane draws a sample and solves for its roots; samples with a valid
+// root go to a per-wavefront queue in LDS, and whenever 64 are queued (and
+// at the end of the item) the wavefront evaluates them on full lanes, so the
+// value, f and deposits run once per valid sample, not on every lane.
 // ---------------------------------------------------------------------------
 constexpr double kRootNorm = 1.0 / (32.0 * kPi * kPi * kPi * kPi * kPi * 16.0);
 
+constexpr int kRootWaves = 4;      // wavefronts per workgroup of the root kernel
+constexpr int kRootQueueLen = 128;  // queued samples per wavefront (< 64 left + 64 new)
+
 template <bool kAlt>
-__global__ __launch_bounds__(256) void collide_roots_kernel(CollideArgs A) {
+__global__ __launch_bounds__(kRootWaves * kWave) void collide_roots_kernel(CollideArgs A) {
   const Grid& G = A.G;
   __shared__ unsigned long long blk_ok;
   __shared__ double blk_mc[2];
   __shared__ double blk_var[kMaxChannels];
   BlockTotals blk{&blk_ok, blk_mc, blk_var};
+  __shared__ Channel s_ch[kMaxChannels];
+  __shared__ int s_group[kMaxChannels];
+  // Samples with at least one valid root, queued per wavefront: the uniform
+  // momentum (k2 or k4), k3x, k3y, the two roots, and which roots hold.
+  __shared__ double rq[kRootWaves][7][kRootQueueLen];
+  __shared__ uint32_t rm[kRootWaves][kRootQueueLen];
+  for (int i = threadIdx.x; i < A.n_group; i += blockDim.x) s_group[i] = A.group[i];
+  for (int i = threadIdx.x; i < A.n_channels; i += blockDim.x) s_ch[i] = A.chans[i];
   blk.init();
   const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int nwaves = gridDim.x * blockDim.x / kWave;
   const long long n_items = (long long)G.cells * A.n_group * G.nodes;
@@ -759,8 +779,8 @@ __global__ __launch_bounds__(256) void collide_roots_kernel(CollideArgs A) {
     const int p1_lin = (int)(w % G.nodes);
     const int gi = (int)((w / G.nodes) % A.n_group);
     const int cell = (int)(w / ((long long)G.nodes * A.n_group));
-    const int ci = A.group[gi];
-    const Channel ch = A.chans[ci];
+    const int ci = s_group[gi];
+    const Channel ch = s_ch[ci];
     Item it;
     load_item(it, A, ch, cell, p1_lin);
     if (!(it.E1 > 0.0)) {  // massless p = 0 node: zero measure
@@ -782,71 +802,38 @@ __global__ __launch_bounds__(256) void collide_roots_kernel(CollideArgs A) {
     const double coef = (A.symmetric ? ch.w : ch.sigma) * V5 / (double)A.n_samples * G.g4 * kRootNorm / it.E1;
     double dsum = 0.0, ssum = 0.0, dsq = 0.0;
     int n_ok = 0;
-    for (int s = lane; s < A.n_samples; s += kWave) {
-      uint32_t x0 = (uint32_t)s, x1 = (uint32_t)p1_lin, x2 = (uint32_t)cell, x3 = ((uint32_t)ch.code << 8) | 2u;
-      philox4x32_10(x0, x1, x2, x3, A.key0, A.key1);
-      double u[5];
-      five_uniforms(x0, x1, x2, x3, u);
-      double q[3];  // k2 (the paper's choice) or k4 (the alternative), uniform in the box
-      for (int a = 0; a < 3; ++a) q[a] = fma(2.0 * G.ph[a], u[a], -G.ph[a]);
-      const double k3x = fma(2.0 * G.ph[0], u[3], -G.ph[0]);
-      const double k3y = fma(2.0 * G.ph[1], u[4], -G.ph[1]);
+    // The value of one queued sample: the sum over its valid roots, with
+    // their deposits.
+    auto finish = [&](unsigned slot) {
+      const double q[3] = {rq[wid][0][slot], rq[wid][1][slot], rq[wid][2][slot]};
+      const double k3x = rq[wid][3][slot], k3y = rq[wid][4][slot];
+      const uint32_t roots = rm[wid][slot];
       const double a3 = k3x * k3x + k3y * k3y + it.m3sq;
       const double Eq = sqrt64(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + (kAlt ? it.m4sq : it.m2sq));
-      double Q[3], lin, half, den, W = 0.0, D = 0.0, C = 0.0;
-      bool any;
-      if (!kAlt) {
-        W = it.E1 + Eq;
-        for (int a = 0; a < 3; ++a) Q[a] = it.p1[a] + q[a];
-        const double b = (Q[0] - k3x) * (Q[0] - k3x) + (Q[1] - k3y) * (Q[1] - k3y) + it.m4sq;
-        C = W * W + a3 - b - Q[2] * Q[2];
-        den = W * W - Q[2] * Q[2];
-        const double H = C * C - 4.0 * a3 * den;
-        any = H >= 0.0 && den > 0.0;
-        lin = C * Q[2];
-        half = any ? W * sqrt64(H) : 0.0;
-      } else {
-        D = it.E1 - Eq;
-        for (int a = 0; a < 3; ++a) Q[a] = q[a] - it.p1[a];
-        C = 2.0 * (k3x * Q[0] + k3y * Q[1]) + (Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2]) + it.m2sq - it.m3sq - D * D;
-        den = Q[2] * Q[2] - D * D;
-        const double H = C * C + 4.0 * a3 * den;
-        any = H >= 0.0 && den != 0.0 && D != 0.0;
-        lin = -C * Q[2];
-        half = any ? fabs(D) * sqrt64(H) : 0.0;
-      }
       double vsample = 0.0;
-      const double inv_2den = any ? rcp64(2.0 * den) : 0.0;
 #pragma unroll 1
-      for (int r = 0; r < 2 && any; ++r) {
-        const double z = (lin + (r == 0 ? half : -half)) * inv_2den;
+      for (int r = 0; r < 2; ++r) {
+        if (!((roots >> r) & 1u)) continue;
+        const double z = rq[wid][5 + r][slot];
         const double E3 = sqrt64(a3 + z * z);
         double p2[3], p3[3] = {k3x, k3y, z}, p4[3], E2, E4, J;
         if (!kAlt) {
-          if (!(C + 2.0 * Q[2] * z > 0.0) || !(E3 < W)) continue;
           for (int a = 0; a < 3; ++a) {
             p2[a] = q[a];
-            p4[a] = Q[a] - p3[a];
+            p4[a] = it.p1[a] + q[a] - p3[a];
           }
           E2 = Eq;
           E4 = sqrt64(p4[0] * p4[0] + p4[1] * p4[1] + p4[2] * p4[2] + it.m4sq);
           J = fabs(z * rcp64(E3) - p4[2] * rcp64(E4));
         } else {
-          if (!((C + 2.0 * Q[2] * z) * D < 0.0) || !(E3 - D > 0.0)) continue;
           for (int a = 0; a < 3; ++a) {
             p4[a] = q[a];
-            p2[a] = p3[a] + Q[a];
+            p2[a] = p3[a] + (q[a] - it.p1[a]);
           }
           E4 = Eq;
           E2 = sqrt64(p2[0] * p2[0] + p2[1] * p2[1] + p2[2] * p2[2] + it.m2sq);
           J = fabs(p2[2] * rcp64(E2) - z * rcp64(E3));
         }
-        bool inside = true;
-        for (int a = 0; a < 3; ++a) {
-          inside = inside && fabs(p3[a]) <= G.ph[a];
-          inside = inside && (kAlt ? fabs(p2[a]) <= G.ph[a] : fabs(p4[a]) <= G.ph[a]);
-        }
-        if (!inside) continue;
         ++n_ok;
         double Pq[3], d13[3], d14[3];
         for (int a = 0; a < 3; ++a) {
@@ -887,6 +874,84 @@ __global__ __launch_bounds__(256) void collide_roots_kernel(CollideArgs A) {
       }
       dsum += vsample;
       dsq = fma(vsample, vsample, dsq);
+    };
+    unsigned head = 0, tail = 0;  // ring positions (wave-uniform)
+    for (int base = 0; base < A.n_samples; base += kWave) {
+      const int s = base + lane;
+      uint32_t roots = 0;
+      double q[3], k3x = 0.0, k3y = 0.0, zr[2] = {0.0, 0.0};
+      if (s < A.n_samples) {
+        uint32_t x0 = (uint32_t)s, x1 = (uint32_t)p1_lin, x2 = (uint32_t)cell, x3 = ((uint32_t)ch.code << 8) | 2u;
+        philox4x32_10(x0, x1, x2, x3, A.key0, A.key1);
+        double u[5];
+        five_uniforms(x0, x1, x2, x3, u);
+        for (int a = 0; a < 3; ++a) q[a] = fma(2.0 * G.ph[a], u[a], -G.ph[a]);
+        k3x = fma(2.0 * G.ph[0], u[3], -G.ph[0]);
+        k3y = fma(2.0 * G.ph[1], u[4], -G.ph[1]);
+        const double a3 = k3x * k3x + k3y * k3y + it.m3sq;
+        const double Eq = sqrt64(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + (kAlt ? it.m4sq : it.m2sq));
+        double Q[3], lin, half, den, W = 0.0, D = 0.0, C = 0.0;
+        bool any;
+        if (!kAlt) {
+          W = it.E1 + Eq;
+          for (int a = 0; a < 3; ++a) Q[a] = it.p1[a] + q[a];
+          const double b = (Q[0] - k3x) * (Q[0] - k3x) + (Q[1] - k3y) * (Q[1] - k3y) + it.m4sq;
+          C = W * W + a3 - b - Q[2] * Q[2];
+          den = W * W - Q[2] * Q[2];
+          const double H = C * C - 4.0 * a3 * den;
+          any = H >= 0.0 && den > 0.0;
+          lin = C * Q[2];
+          half = any ? W * sqrt64(H) : 0.0;
+        } else {
+          D = it.E1 - Eq;
+          for (int a = 0; a < 3; ++a) Q[a] = q[a] - it.p1[a];
+          C = 2.0 * (k3x * Q[0] + k3y * Q[1]) + (Q[0] * Q[0] + Q[1] * Q[1] + Q[2] * Q[2]) + it.m2sq - it.m3sq - D * D;
+          den = Q[2] * Q[2] - D * D;
+          const double H = C * C + 4.0 * a3 * den;
+          any = H >= 0.0 && den != 0.0 && D != 0.0;
+          lin = -C * Q[2];
+          half = any ? fabs(D) * sqrt64(H) : 0.0;
+        }
+        const double inv_2den = any ? rcp64(2.0 * den) : 0.0;
+        for (int r = 0; r < 2 && any; ++r) {
+          const double z = (lin + (r == 0 ? half : -half)) * inv_2den;
+          const double E3 = sqrt64(a3 + z * z);
+          bool ok;
+          if (!kAlt) ok = (C + 2.0 * Q[2] * z > 0.0) && (E3 < W);
+          else ok = ((C + 2.0 * Q[2] * z) * D < 0.0) && (E3 - D > 0.0);
+          const double p3[3] = {k3x, k3y, z};
+          for (int a = 0; a < 3; ++a) {
+            const double other = kAlt ? p3[a] + Q[a] : Q[a] - p3[a];  // p2 or p4
+            ok = ok && fabs(p3[a]) <= G.ph[a] && fabs(other) <= G.ph[a];
+          }
+          if (ok) {
+            roots |= 1u << r;
+            zr[r] = z;
+          }
+        }
+      }
+      const unsigned long long mask = __ballot(roots != 0u);
+      if (roots) {
+        const unsigned slot = (tail + (unsigned)__popcll(mask & ((1ull << lane) - 1ull))) & (kRootQueueLen - 1);
+        for (int a = 0; a < 3; ++a) rq[wid][a][slot] = q[a];
+        rq[wid][3][slot] = k3x;
+        rq[wid][4][slot] = k3y;
+        rq[wid][5][slot] = zr[0];
+        rq[wid][6][slot] = zr[1];
+        rm[wid][slot] = roots;
+      }
+      tail += (unsigned)__popcll(mask);
+      if (tail - head >= (unsigned)kWave) {
+        wave_lds_sync();
+        finish((head + lane) & (kRootQueueLen - 1));
+        head += kWave;
+        wave_lds_sync();
+      }
+    }
+    if (tail != head) {  // the last, partial batch
+      wave_lds_sync();
+      if ((unsigned)lane < tail - head) finish((head + lane) & (kRootQueueLen - 1));
+      wave_lds_sync();
     }
     dsum = wave_sum(dsum);
     if (A.scale) ssum = wave_sum(ssum);
@@ -1298,7 +1363,7 @@ hipError_t launch_record(const CollideArgs& a, int n_per_item, long long item_st
 // ---------------------------------------------------------------------------
 hipError_t launch_collide_roots(const CollideArgs& a, bool alt, hipStream_t stream) {
   const long long items = (long long)a.G.cells * a.n_group * a.G.nodes;
-  const int threads = 256;
+  const int threads = kRootWaves * kWave;  // the per-wavefront queues are sized for this
   long long blocks = (items * kWave + threads - 1) / threads;
   if (blocks > 4096) blocks = 4096;  // 16 waves per CU; the rest by the grid-stride loop
   if (blocks < 1) blocks = 1;

@@ -359,6 +359,32 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Wavefront sums.  The FP64 and root kernels, with one short item per
+// wavefront, use DPP: two quad permutations and two rotations within
+// each 16-lane row leave every lane with its row's sum; the four row sums
+// are read from lanes 0, 16, 32, 48 and added in a fixed order.  Every lane
+// must be active.
+template <int kCtrl>
+__device__ __forceinline__ int dpp_i32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, kCtrl, 0xF, 0xF, false);
+}
+
+template <int kCtrl>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)dpp_i32<kCtrl>((int)(unsigned)b);
+  const unsigned hi = (unsigned)dpp_i32<kCtrl>((int)(unsigned)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Butterfly sums through lane permutes, for the FP32 kernel (long items).
 __device__ __forceinline__ int wave_count(int v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
@@ -369,6 +395,23 @@ __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
   return v;
+}
+
+__device__ __forceinline__ int wave_count_dpp(int v) {
+  v += dpp_i32<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_i32<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_i32<0x124>(v);  // row_ror:4
+  v += dpp_i32<0x128>(v);  // row_ror:8
+  return (__builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16)) +
+         (__builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48));
+}
+
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_f64<0xB1>(v);
+  v += dpp_f64<0x4E>(v);
+  v += dpp_f64<0x124>(v);
+  v += dpp_f64<0x128>(v);
+  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
 // ---------------------------------------------------------------------------
@@ -709,10 +752,10 @@ __global__ __launch_bounds__(256) void collide_f64_kernel(CollideArgs A) {
         }
       }
     }
-    dsum = wave_sum(dsum);
-    if (A.scale) ssum = wave_sum(ssum);
-    dsq = wave_sum(dsq);
-    const int ok_total = wave_count(n_ok);
+    dsum = wave_sum_dpp(dsum);
+    if (A.scale) ssum = wave_sum_dpp(ssum);
+    dsq = wave_sum_dpp(dsq);
+    const int ok_total = wave_count_dpp(n_ok);
     if (lane == 0) {
       blk.add(ok_total, item_variance(dsum, dsq, A.n_samples), dsum * dsum, ci);
       atomicAdd(Ac[0] + p1_lin, dsum);
@@ -953,10 +996,10 @@ __global__ __launch_bounds__(kRootWaves * kWave) void collide_roots_kernel(Colli
       if ((unsigned)lane < tail - head) finish((head + lane) & (kRootQueueLen - 1));
       wave_lds_sync();
     }
-    dsum = wave_sum(dsum);
-    if (A.scale) ssum = wave_sum(ssum);
-    dsq = wave_sum(dsq);
-    const int ok_total = wave_count(n_ok);
+    dsum = wave_sum_dpp(dsum);
+    if (A.scale) ssum = wave_sum_dpp(ssum);
+    dsq = wave_sum_dpp(dsq);
+    const int ok_total = wave_count_dpp(n_ok);
     if (lane == 0) {
       blk.add(ok_total, item_variance(dsum, dsq, A.n_samples), dsum * dsum, ci);
       atomicAdd(Ac[0] + p1_lin, dsum);

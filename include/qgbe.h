@@ -275,7 +275,9 @@ qgbe_status qgbe_observables(qgbe_ctx* ctx, qgbe_stats* st);
  *         component k is drawn when thr[k] <= x < thr[k+1] (thr[K] = 2^32)
  *   mu    [rows][K][5] float32 location in logit space
  *   sigma [rows][K][5] float32 scale in logit space (> 0)
- * rows = channels * nodes.  K in 1..16.  Copied into the workspace. */
+ * rows = channels * nodes.  K in 1..16.  Copied into the workspace.  An FP32
+ * context's learned sampler takes K <= 8: with more components its collision
+ * term and step return QGBE_EUNSUPPORTED before any device work. */
 qgbe_status qgbe_set_proposal_table(qgbe_ctx* ctx, int32_t K, const uint32_t* thr,
                                     const float* mu, const float* sigma, int32_t on_device);
 

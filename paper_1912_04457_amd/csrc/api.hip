@@ -513,6 +513,8 @@ qgbe_status qgbe_collision_term_ex(qgbe_ctx* c, int32_t n_samples, int32_t sampl
   if (n_samples < 1) return fail(QGBE_EINVAL, "n_samples must be >= 1");
   if (sampler < QGBE_SAMPLER_UNIFORM || sampler > QGBE_SAMPLER_ROOTS_ALT) return fail(QGBE_EINVAL, "bad sampler");
   if (sampler == QGBE_SAMPLER_LEARNED && !c->K) return fail(QGBE_ESTATE, "no proposal table installed");
+  if (sampler == QGBE_SAMPLER_LEARNED && c->d.precision == QGBE_FP32 && c->K > kMixKF32)
+    return fail(QGBE_EUNSUPPORTED, "the FP32 learned sampler takes at most 8 mixture components (FP64 takes 16)");
   HIP_TRY(hipSetDevice(c->d.device), "hipSetDevice");
   const size_t n = field_len(c);
   double* A = on_device ? A_out : c->d_A;
@@ -601,6 +603,8 @@ qgbe_status qgbe_step(qgbe_ctx* c, double dt_fm, int32_t n_samples, int32_t samp
   if (n_samples < 1 || n_steps < 0) return fail(QGBE_EINVAL, "n_samples >= 1 and n_steps >= 0 required");
   if (sampler < QGBE_SAMPLER_UNIFORM || sampler > QGBE_SAMPLER_ROOTS_ALT) return fail(QGBE_EINVAL, "bad sampler");
   if (sampler == QGBE_SAMPLER_LEARNED && !c->K) return fail(QGBE_ESTATE, "no proposal table installed");
+  if (sampler == QGBE_SAMPLER_LEARNED && c->d.precision == QGBE_FP32 && c->K > kMixKF32)
+    return fail(QGBE_EUNSUPPORTED, "the FP32 learned sampler takes at most 8 mixture components (FP64 takes 16)");
   HIP_TRY(hipSetDevice(c->d.device), "hipSetDevice");
   const size_t n = field_len(c);
   qgbe_status result = QGBE_OK;

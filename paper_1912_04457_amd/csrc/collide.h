@@ -9,6 +9,10 @@ namespace qgbe {
 // one of kStripes addresses, so same-address atomics do not serialise.
 constexpr int kStripes = 64;
 
+// Mixture components the FP32 learned sampler takes (its per-wave LDS row of
+// component constants is laid out for this many); the FP64 path takes 16.
+constexpr int kMixKF32 = 8;
+
 struct CollideArgs {
   Grid G;
   const Channel* chans;   // device channel table (all channels)

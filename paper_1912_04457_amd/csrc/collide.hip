@@ -459,6 +459,7 @@ __device__ __forceinline__ void mix_draw(const uint32_t x[8], const uint32_t* __
 // sigma (40).
 constexpr int kMixSigma = 89;
 constexpr int kMixRow = kMixSigma + 40;
+static_assert(5 * kMixKF32 == 40 && kMixKF32 <= 8, "row layout: 8 components");
 
 // The same draw for the FP32 kernel: component parameters from the wave's
 // LDS row (see mix_prepare_f32), thresholds from the (wave-uniform) table

@@ -98,14 +98,22 @@ __global__ void silu_backward_kernel(const float* __restrict__ dH, const float* 
   }
 }
 
-// out[n] += sum over rows of M[row][n] (column sums for the bias gradients)
-__global__ void colsum_kernel(const float* __restrict__ M, int rows, int cols, float* __restrict__ out) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= cols) return;
-  const int r0 = blockIdx.y * 256, r1 = min(rows, r0 + 256);
+// out[n] += sum over rows of M[row][n] (column sums for the bias gradients).
+// A workgroup sums a chunk of kColsumRows rows of 64 columns: four row phases
+// of 64 lanes, combined in LDS, one atomic per column.
+constexpr int kColsumRows = 64;
+__global__ __launch_bounds__(256) void colsum_kernel(const float* __restrict__ M, int rows, int cols,
+                                                     float* __restrict__ out) {
+  __shared__ float part[4][64];
+  const int lane = threadIdx.x & 63, ph = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + lane;
+  const int r0 = blockIdx.y * kColsumRows, r1 = min(rows, r0 + kColsumRows);
   float s = 0.f;
-  for (int r = r0; r < r1; ++r) s += M[(size_t)r * cols + n];
-  atomicAdd(&out[n], s);
+  if (n < cols)
+    for (int r = r0 + ph; r < r1; r += 4) s += M[(size_t)r * cols + n];
+  part[ph][lane] = s;
+  __syncthreads();
+  if (ph == 0 && n < cols) atomicAdd(&out[n], (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]));
 }
 
 __global__ void sum_kernel(const float* __restrict__ w, int stride, int rows, double* out) {
@@ -404,8 +412,8 @@ hipError_t launch_silu_backward(const float* dH, const float* Z, float* dZ, __bf
 }
 
 hipError_t launch_colsum(const float* M, int rows, int cols, float* out, hipStream_t st) {
-  dim3 grid((cols + 127) / 128, (rows + 255) / 256);
-  hipLaunchKernelGGL(colsum_kernel, grid, dim3(128), 0, st, M, rows, cols, out);
+  dim3 grid((cols + 63) / 64, (rows + kColsumRows - 1) / kColsumRows);
+  hipLaunchKernelGGL(colsum_kernel, grid, dim3(256), 0, st, M, rows, cols, out);
   return hipGetLastError();
 }
 

@@ -293,3 +293,33 @@ def test_spatial_seven_species_learned_steps(O):
     print(f"[spatial learned] N_total relative drift over 5 steps {drift:.2e}", flush=True)
     assert drift <= 1e-12
     assert all(np.isfinite(st["E_total"]) for st in stats)
+
+
+def test_learned_sixteen_components(O):
+    """A host-set table of 16 components: the FP64 learned sampler agrees with
+    the oracle; an FP32 context (whose LDS row of component constants holds 8)
+    refuses it with QGBE_EUNSUPPORTED instead of running."""
+    _case("learned K=16 fp64 parity, fp32 refusal")
+    wl = SMALL_7
+    f = W.random_f(41, wl.cells, wl.nodes)
+    g = O.Grid(n_x=wl.n_x, n_p=wl.n_p, x_half=wl.x_half, p_half=wl.p_half, species_mask=wl.species_mask)
+    rows = len(O.channels(g)) * wl.nodes
+    thr, mu, sg = W.random_mog_table(42, rows, K=16, alpha=0.1, mu_scale=1.0, log_sigma=(-1.0, 0.5))
+    with qgbe.Solver(**_kw(wl), precision=qgbe.FP64) as s:
+        s.set_f(f)
+        qgbe.qgbe_set_step_index(s.ctx, 3)
+        qgbe.qgbe_set_proposal_table(s.ctx, thr, mu, sg)
+        A, _, _, _ = s.collision(100, sampler=qgbe.SAMPLER_LEARNED)
+    m = O.masses(g, f)
+    A_ref, S_ref, _ = O.collision_learned(g, f, m, SEED, 3, 100, thr, mu, sg)
+    assert np.all(np.abs(A - A_ref) <= 1e-10 * S_ref + 1e-300)
+    with qgbe.Solver(**_kw(wl), precision=qgbe.FP32) as s:
+        s.set_f(f)
+        qgbe.qgbe_set_proposal_table(s.ctx, thr, mu, sg)
+        for call in (lambda: s.collision(100, sampler=qgbe.SAMPLER_LEARNED),
+                     lambda: s.step(0.01, 100, n_steps=1, sampler=qgbe.SAMPLER_LEARNED)):
+            with pytest.raises(qgbe.QgbeError) as e:
+                call()
+            assert e.value.status == qgbe.EUNSUPPORTED
+        A, _, _, _ = s.collision(100, sampler=qgbe.SAMPLER_UNIFORM)   # the context still works
+        assert np.isfinite(A).all()

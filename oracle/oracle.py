@@ -108,6 +108,8 @@ def lib():
         _lib.ref_drift.argtypes = [p, p, p, i32, p]
         _lib.ref_observables.restype = i32
         _lib.ref_observables.argtypes = [p, p, p, p, p, p]
+        _lib.ref_stencil.restype = i32
+        _lib.ref_stencil.argtypes = [p, C.c_int64, p, p, p]
     return _lib
 
 
@@ -371,6 +373,25 @@ def drift(grid: Grid, f, mass2, scheme: str = "upwind") -> np.ndarray:
     if lib().ref_drift(C.byref(g), _ptr(f), _ptr(mass2), {"upwind": 0, "central": 1}[scheme], _ptr(D)):
         raise ValueError("bad grid")
     return D
+
+
+def stencil(grid: Grid, pts) -> tuple:
+    """The trilinear stencil of the collision term (reading R2: per axis the
+    stencil coordinate is clamped to the outermost node centres) for momenta
+    pts [n, 3]: node indices [n, 8] and weights [n, 8]."""
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 3)
+    idx = np.zeros((len(pts), 8), dtype=np.int64)
+    w = np.zeros((len(pts), 8))
+    g = grid.c()
+    if lib().ref_stencil(C.byref(g), len(pts), _ptr(pts), _ptr(idx), _ptr(w)):
+        raise ValueError("bad grid")
+    return idx, w
+
+
+def interpolate(grid: Grid, f_cell, pts) -> np.ndarray:
+    """f of one (species, cell) row [nodes] at momenta pts [n, 3]."""
+    idx, w = stencil(grid, pts)
+    return (w * np.asarray(f_cell, dtype=np.float64)[idx]).sum(1)
 
 
 def observables(grid: Grid, f, mass2) -> dict:

@@ -752,6 +752,12 @@ static int check_grid(const ref_grid* g) {
   return 0;
 }
 
+int32_t ref_stencil(const ref_grid* g, int64_t n, const double* pts, int64_t* idx, double* w) {
+  if (check_grid(g) || n < 0) return -1;
+  for (int64_t i = 0; i < n; ++i) cic_stencil(g, pts + 3 * i, idx + 8 * i, w + 8 * i);
+  return 0;
+}
+
 typedef enum { ITEM_UNIFORM, ITEM_LEARNED } item_kind;
 
 typedef struct {

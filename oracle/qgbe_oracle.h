@@ -178,6 +178,10 @@ int32_t ref_collision_points(const ref_grid* g, const double* f, const double* m
 int32_t ref_drift(const ref_grid* g, const double* f, const double* mass2,
                   int32_t scheme, double* D_out);
 
+/* the trilinear stencil every off-grid f read and every deposit uses, for
+   n momenta pts[n][3]: node indices idx[n][8] and weights w[n][8] */
+int32_t ref_stencil(const ref_grid* g, int64_t n, const double* pts, int64_t* idx, double* w);
+
 /* number, energy and momentum per species (FP64 bookkeeping) */
 int32_t ref_observables(const ref_grid* g, const double* f, const double* mass2,
                         double* N_out /*7*/, double* E_out /*7*/, double* P_out /*7x3*/);

@@ -85,3 +85,35 @@ def test_free_streaming_first_order(O):
     e32, e64 = _free_stream_error(O, 32), _free_stream_error(O, 64)
     assert e64 < 0.05
     assert 1.6 < e32 / e64 < 2.4
+
+
+@pytest.mark.parametrize("scheme", ["upwind", "central"])
+def test_uniform_masses_give_the_textbook_difference(O, scheme):
+    """With the same masses in every cell the force vanishes, the interface
+    velocity is v = p/E itself, and the operator is the textbook difference of
+    v f along each spatial axis over periodic cells: first-order upwind
+    v (f_i - f_{i-1}) / dx for v > 0 and v (f_{i+1} - f_i) / dx for v < 0, or
+    the central v (f_{i+1} - f_{i-1}) / (2 dx), built here from array shifts
+    (reading R13 on the interface average and the periodic cells)."""
+    n_x = (5, 4, 3)
+    g = O.Grid(n_x=n_x, n_p=(4, 3, 5), x_half=(3.0, 2.0, 1.5), p_half=(2.0, 2.5, 1.5), species_mask=0x7F)
+    rng = np.random.Generator(np.random.PCG64(15))
+    f = rng.uniform(0.0, 1.0, (7, g.cells, g.nodes))
+    m2 = O.constant_masses(g, [0.05, 0.07, 0.09, 0.05, 0.07, 0.09, 0.3])
+    D = O.drift(g, f, m2, scheme)
+    q = g.momenta()
+    dx = [2.0 * h / n for h, n in zip(g.x_half, n_x)]
+    F = f.reshape(7, *n_x, g.nodes)
+    ref = np.zeros_like(F)
+    for sp in range(7):
+        v = q / np.sqrt((q ** 2).sum(1) + m2[sp, 0])[:, None]
+        for a in range(3):
+            fs = F[sp]
+            fp = np.roll(fs, -1, axis=a)      # f_{i+1}
+            fm = np.roll(fs, +1, axis=a)      # f_{i-1}
+            va = v[:, a]
+            if scheme == "upwind":
+                ref[sp] += np.where(va > 0, va * (fs - fm), va * (fp - fs)) / dx[a]
+            else:
+                ref[sp] += va * (fp - fm) / (2.0 * dx[a])
+    assert np.allclose(D, ref.reshape(D.shape), rtol=1e-12, atol=1e-12 * np.abs(ref).max())

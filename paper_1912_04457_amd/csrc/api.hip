@@ -205,6 +205,17 @@ qgbe_status run_collide(qgbe_ctx* c, int n_samples, int sampler, double* A, doub
     const long long items = (long long)c->G.cells * g.count * c->G.nodes;
     long long chunk = items / 2048;
     chunk = std::max<long long>(waves, std::min<long long>(512, chunk));
+    // Every workgroup zeroes and flushes its LDS accumulators; with few
+    // samples per point that costs as much as the samples themselves, so the
+    // chunk grows until the flush entries are at most a quarter of the
+    // workgroup's samples, keeping at least two workgroups per compute unit
+    // (measured: a quarter beats an eighth, a half and one).
+    const long long acc = c->d.symmetric ? (long long)std::min(g.nslot, std::max(g.lds_acc[l], 0)) * g.win[l] : 0;
+    if (acc > 0 && chunk * n_samples < 4 * acc) {
+      const long long want = (4 * acc + n_samples - 1) / n_samples;
+      const long long fill = items / (2LL * c->n_cu);
+      chunk = std::max(chunk, std::min(want, fill));
+    }
     chunk = (chunk + waves - 1) / waves * waves;
     chunk = std::min<long long>(chunk, (c->G.nodes + waves - 1) / waves * waves);
     a.chunk_items = (int)chunk;
@@ -356,6 +367,9 @@ qgbe_status qgbe_init_grid(const qgbe_grid_desc* desc, qgbe_ctx** out) {
   c->lds_budget[0] = lds_budget[0];
   c->lds_budget[1] = lds_budget[1];
   c->lds_budget_queue = lds_budget[2];
+  int n_cu = 0;
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, desc->device) == hipSuccess && n_cu > 0)
+    c->n_cu = n_cu;
   plan_groups(c);
   const size_t n = field_len(c);
   std::vector<int> all(std::max(1, c->nch));

@@ -96,6 +96,7 @@ struct qgbe_ctx {
   size_t ws = 0;
   size_t lds_budget[2] = {0, 0};   // dynamic LDS per workgroup [uniform, learned sampler]
   size_t lds_budget_queue = 0;     // dynamic LDS of the compacting uniform-sampler variant
+  int n_cu = 256;                  // compute units of the device
 };
 
 namespace qgbe {

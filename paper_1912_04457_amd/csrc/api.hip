@@ -208,12 +208,14 @@ qgbe_status run_collide(qgbe_ctx* c, int n_samples, int sampler, double* A, doub
     // Every workgroup zeroes and flushes its LDS accumulators; with few
     // samples per point that costs as much as the samples themselves, so the
     // chunk grows until the flush entries are at most a quarter of the
-    // workgroup's samples, keeping at least two workgroups per compute unit
-    // (measured: a quarter beats an eighth, a half and one).
+    // workgroup's samples (measured: a quarter beats an eighth, a half and
+    // one), keeping at least two workgroups per compute unit, or one where
+    // even then the flush would outweigh the samples.
     const long long acc = c->d.symmetric ? (long long)std::min(g.nslot, std::max(g.lds_acc[l], 0)) * g.win[l] : 0;
     if (acc > 0 && chunk * n_samples < 4 * acc) {
       const long long want = (4 * acc + n_samples - 1) / n_samples;
-      const long long fill = items / (2LL * c->n_cu);
+      long long fill = items / (2LL * c->n_cu);
+      if (fill * n_samples < acc) fill = items / c->n_cu;
       chunk = std::max(chunk, std::min(want, fill));
     }
     chunk = (chunk + waves - 1) / waves * waves;

@@ -34,9 +34,10 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 // I_Y = sum_p dV/(2pi)^3 f_Y / (2 E_Y) per cell, E_Y from the lagged masses
 // (or |p| when there are none; a node at p = 0 then adds 0).  Stage 1: block
-// (cell, chunk) sums kMassChunk nodes of every species; stage 2: one thread
-// per cell adds its chunks in order (deterministic) and applies Eq. mg / mq.
-constexpr int kMassChunk = 2048;
+// (cell, chunk) sums kMassChunk nodes of every species; stage 2: one block
+// per cell adds its chunks in a fixed order (deterministic) and applies
+// Eq. mg / mq.
+constexpr int kMassChunk = 256;  // nodes per block: a single cell of 30^3 nodes still fills 100+ CUs
 
 __host__ __device__ inline int mass_chunks(const Grid& G) { return (G.nodes + kMassChunk - 1) / kMassChunk; }
 
@@ -63,15 +64,16 @@ __global__ __launch_bounds__(kBlock) void mass_partial(Grid G, const double* __r
 
 __global__ __launch_bounds__(kBlock) void mass_final(Grid G, const double* __restrict__ part, int chunks,
                                                      double* mass2) {
-  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
-  if (cell >= G.cells) return;
+  __shared__ double sh[kBlock / 64];
+  const int cell = blockIdx.x;  // one block per cell; its threads stride over the chunks
   const double meas = G.dp[0] * G.dp[1] * G.dp[2] / (8.0 * kPi * kPi * kPi);
   double I[kSpecies];
   for (int sp = 0; sp < kSpecies; ++sp) {
     double t = 0.0;
-    for (int c = 0; c < chunks; ++c) t += part[((size_t)cell * chunks + c) * kSpecies + sp];
-    I[sp] = t * meas;
+    for (int c = threadIdx.x; c < chunks; c += blockDim.x) t += part[((size_t)cell * chunks + c) * kSpecies + sp];
+    I[sp] = block_sum(t, sh) * meas;  // fixed order: deterministic
   }
+  if (threadIdx.x != 0) return;
   // SU(3): dA = 8, CA = 3, CF = 4/3; N_g = 16, N_q = 6
   const double CF = 4.0 / 3.0;
   double q = 0.0;
@@ -349,8 +351,7 @@ hipError_t launch_masses(const Grid& G, const double* f, const double* lag, doub
                          hipStream_t st) {
   const int chunks = mass_chunks(G);
   hipLaunchKernelGGL(mass_partial, dim3(chunks * G.cells), dim3(kBlock), 0, st, G, f, lag, scratch);
-  hipLaunchKernelGGL(mass_final, dim3((G.cells + kBlock - 1) / kBlock), dim3(kBlock), 0, st, G, scratch, chunks,
-                     mass2);
+  hipLaunchKernelGGL(mass_final, dim3(G.cells), dim3(kBlock), 0, st, G, scratch, chunks, mass2);
   return hipGetLastError();
 }
 

@@ -453,7 +453,14 @@ class Solver:
         qgbe_observables(self.ctx, st)
         return st.as_dict()
 
-    def step(self, dt_fm: float, n_samples: int, n_steps: int = 1, sampler: int = SAMPLER_UNIFORM):
+    def step(self, dt_fm: float, n_samples: int, n_steps: int = 1, sampler: int = SAMPLER_UNIFORM,
+             last_only: bool = False):
+        """n_steps steps; the statistics of every step, or with last_only those
+        of the last one only (the steps before run without the per-step
+        reductions and host synchronisation)."""
+        if last_only and n_steps > 1:
+            qgbe_step(self.ctx, dt_fm, n_samples, sampler, n_steps - 1, None)
+            n_steps = 1
         stats = (Stats * n_steps)()
         qgbe_step(self.ctx, dt_fm, n_samples, sampler, n_steps, stats)
         return [s.as_dict() for s in stats]

@@ -78,7 +78,7 @@ def evolve(kind: str = "gluon", n_p=(20, 20, 20), p_half=(2.0, 2.0, 2.0), f0: fl
         done = 0
         while done < steps:
             k = min(every, steps - done)
-            st = s.step(dt_fm, samples, n_steps=k)[-1]
+            st = s.step(dt_fm, samples, n_steps=k, last_only=True)[0]
             done += k
             yield record(done, st)
 

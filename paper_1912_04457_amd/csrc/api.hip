@@ -144,11 +144,12 @@ void plan_groups(qgbe_ctx* c) {
       const size_t budget = c->lds_budget[l];
       if (c->d.symmetric && budget < acc_b) {
         // one slot's FP64 accumulators exceed LDS: node windows, one launch
-        // per window and slot, the same samples in each; f from the quads
-        const int fit = (int)(budget / sizeof(double));
+        // per window holding every slot's accumulators for that window, the
+        // same samples in each; f from the quads
+        const int fit = (int)(budget / (sizeof(double) * nslot));
         const int n_win = (c->G.nodes + fit - 1) / fit;
         g.win[l] = (c->G.nodes + n_win - 1) / n_win;
-        g.lds_acc[l] = 1;
+        g.lds_acc[l] = nslot;
         g.lds_tiles[l] = 0;
         continue;
       }

@@ -257,9 +257,11 @@ qgbe_status qgbe_collision_term_ex(qgbe_ctx* ctx, int32_t n_samples, int32_t sam
  *   f += dt (A / (N_Y hbar c) - D[f]) -> observables.
  * dt_fm in fm/c, hbar c = 0.1973269804 GeV fm.  Non-evolving species are
  * frozen.  The sampler is as in qgbe_collision_term (a network-built table is
- * re-evaluated at every step).  per_step: n_steps entries or NULL (their
- * t_step_ms covers masses, table, collision term and update).  Returns
- * QGBE_ENUMERIC (after finishing the step) if f became non-finite. */
+ * re-evaluated at every step).  per_step: n_steps entries (their t_step_ms
+ * covers masses, table, collision term and update; each step then waits for
+ * its statistics) or NULL (the steps run without the per-step reductions and
+ * without synchronising the host).  With per_step, returns QGBE_ENUMERIC
+ * (after finishing the step) if f became non-finite. */
 qgbe_status qgbe_step(qgbe_ctx* ctx, double dt_fm, int32_t n_samples, int32_t sampler,
                       int32_t n_steps, qgbe_stats* per_step);
 

@@ -660,11 +660,18 @@ struct BlockTotals {
 
 // ---------------------------------------------------------------------------
 // FP64 kernel: f read from the FP64 field in global memory, deposits as FP64
-// atomics into the output.  This is the reference-precision path.
+// atomics into the output.  This is the reference-precision path.  kPriv (one
+// cell whose 7 species fit in LDS): the symmetric deposits go to a
+// workgroup-private FP64 copy of the cell's output in LDS, flushed once per
+// workgroup, instead of every workgroup's atomics contending for the same
+// few global addresses.
 // ---------------------------------------------------------------------------
-template <bool kLearned>
+template <bool kLearned, bool kPriv>
 __global__ __launch_bounds__(256) void collide_f64_kernel(CollideArgs A) {
   const Grid& G = A.G;
+  extern __shared__ double f64_acc[];  // kPriv: [7][nodes]
+  if (kPriv)
+    for (int i = threadIdx.x; i < kSpecies * G.nodes; i += blockDim.x) f64_acc[i] = 0.0;
   __shared__ unsigned long long blk_ok;
   __shared__ double blk_mc[2];
   __shared__ double blk_var[kMaxChannels];
@@ -742,7 +749,16 @@ __global__ __launch_bounds__(256) void collide_f64_kernel(CollideArgs A) {
       dsq = fma(v, v, dsq);
       const double vs = fabs(wnb) * (gain + loss);
       ssum += vs;
-      if (A.symmetric) {
+      if (kPriv) {
+        deposit<double, double, __HIP_MEMORY_SCOPE_WORKGROUP>(f64_acc + ch.sp[1] * G.nodes, s2, v, G.ox, G.oy);
+        deposit<double, double, __HIP_MEMORY_SCOPE_WORKGROUP>(f64_acc + ch.sp[2] * G.nodes, s3, -v, G.ox, G.oy);
+        deposit<double, double, __HIP_MEMORY_SCOPE_WORKGROUP>(f64_acc + ch.sp[3] * G.nodes, s4, -v, G.ox, G.oy);
+        if (A.scale) {
+          deposit<double, double>(Sc[1], s2, vs, G.ox, G.oy);
+          deposit<double, double>(Sc[2], s3, vs, G.ox, G.oy);
+          deposit<double, double>(Sc[3], s4, vs, G.ox, G.oy);
+        }
+      } else if (A.symmetric) {
         deposit<double, double>(Ac[1], s2, v, G.ox, G.oy);
         deposit<double, double>(Ac[2], s3, -v, G.ox, G.oy);
         deposit<double, double>(Ac[3], s4, -v, G.ox, G.oy);
@@ -764,7 +780,10 @@ __global__ __launch_bounds__(256) void collide_f64_kernel(CollideArgs A) {
       if (A.items) A.items[((size_t)cell * A.n_channels + ci) * G.nodes + p1_lin] = dsum;
     }
   }
-  blk.flush(A);
+  blk.flush(A);  // (begins with a barrier: every wave's deposits are in)
+  if (kPriv)  // one cell: species sp of the output starts at sp * nodes
+    for (int i = threadIdx.x; i < kSpecies * G.nodes; i += blockDim.x)
+      if (f64_acc[i] != 0.0) atomicAdd(A.A + i, f64_acc[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1424,10 +1443,17 @@ hipError_t launch_collide_f64(const CollideArgs& a, hipStream_t stream) {
   long long blocks = (items * kWave + threads - 1) / threads;
   if (blocks > 4096) blocks = 4096;  // 16 waves per CU; the rest by the grid-stride loop
   if (blocks < 1) blocks = 1;
-  if (a.learned)
-    hipLaunchKernelGGL(collide_f64_kernel<true>, dim3((unsigned)blocks), dim3(threads), 0, stream, a);
-  else
-    hipLaunchKernelGGL(collide_f64_kernel<false>, dim3((unsigned)blocks), dim3(threads), 0, stream, a);
+  // one cell whose 7 species fit in the default dynamic LDS: workgroup-private deposits
+  const size_t priv_b = (size_t)kSpecies * a.G.nodes * sizeof(double);
+  const bool priv = a.symmetric && a.G.cells == 1 && priv_b <= 65536;
+  const dim3 grid((unsigned)blocks), block(threads);
+  if (priv) {
+    if (a.learned) hipLaunchKernelGGL(HIP_KERNEL_NAME(collide_f64_kernel<true, true>), grid, block, priv_b, stream, a);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(collide_f64_kernel<false, true>), grid, block, priv_b, stream, a);
+  } else {
+    if (a.learned) hipLaunchKernelGGL(HIP_KERNEL_NAME(collide_f64_kernel<true, false>), grid, block, 0, stream, a);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(collide_f64_kernel<false, false>), grid, block, 0, stream, a);
+  }
   return hipGetLastError();
 }
 

@@ -660,18 +660,18 @@ struct BlockTotals {
 
 // ---------------------------------------------------------------------------
 // FP64 kernel: f read from the FP64 field in global memory, deposits as FP64
-// atomics into the output.  This is the reference-precision path.  kPriv (one
-// cell whose 7 species fit in LDS): the symmetric deposits go to a
-// workgroup-private FP64 copy of the cell's output in LDS, flushed once per
-// workgroup, instead of every workgroup's atomics contending for the same
-// few global addresses.
+// atomics into the output.  This is the reference-precision path.  kPriv (a
+// grid whose whole output fits in LDS): the symmetric deposits go to a
+// workgroup-private FP64 copy of the output in LDS, in the output's layout,
+// flushed once per workgroup, instead of every workgroup's atomics
+// contending for the same few global addresses.
 // ---------------------------------------------------------------------------
 template <bool kLearned, bool kPriv>
 __global__ __launch_bounds__(256) void collide_f64_kernel(CollideArgs A) {
   const Grid& G = A.G;
-  extern __shared__ double f64_acc[];  // kPriv: [7][nodes]
-  if (kPriv)
-    for (int i = threadIdx.x; i < kSpecies * G.nodes; i += blockDim.x) f64_acc[i] = 0.0;
+  extern __shared__ double f64_acc[];  // kPriv: [7][cells][nodes], as the output
+  const int n_out = kPriv ? kSpecies * G.cells * G.nodes : 0;
+  for (int i = threadIdx.x; i < n_out; i += blockDim.x) f64_acc[i] = 0.0;
   __shared__ unsigned long long blk_ok;
   __shared__ double blk_mc[2];
   __shared__ double blk_var[kMaxChannels];
@@ -750,9 +750,9 @@ __global__ __launch_bounds__(256) void collide_f64_kernel(CollideArgs A) {
       const double vs = fabs(wnb) * (gain + loss);
       ssum += vs;
       if (kPriv) {
-        deposit<double, double, __HIP_MEMORY_SCOPE_WORKGROUP>(f64_acc + ch.sp[1] * G.nodes, s2, v, G.ox, G.oy);
-        deposit<double, double, __HIP_MEMORY_SCOPE_WORKGROUP>(f64_acc + ch.sp[2] * G.nodes, s3, -v, G.ox, G.oy);
-        deposit<double, double, __HIP_MEMORY_SCOPE_WORKGROUP>(f64_acc + ch.sp[3] * G.nodes, s4, -v, G.ox, G.oy);
+        deposit<double, double, __HIP_MEMORY_SCOPE_WORKGROUP>(f64_acc + (Ac[1] - A.A), s2, v, G.ox, G.oy);
+        deposit<double, double, __HIP_MEMORY_SCOPE_WORKGROUP>(f64_acc + (Ac[2] - A.A), s3, -v, G.ox, G.oy);
+        deposit<double, double, __HIP_MEMORY_SCOPE_WORKGROUP>(f64_acc + (Ac[3] - A.A), s4, -v, G.ox, G.oy);
         if (A.scale) {
           deposit<double, double>(Sc[1], s2, vs, G.ox, G.oy);
           deposit<double, double>(Sc[2], s3, vs, G.ox, G.oy);
@@ -781,9 +781,8 @@ __global__ __launch_bounds__(256) void collide_f64_kernel(CollideArgs A) {
     }
   }
   blk.flush(A);  // (begins with a barrier: every wave's deposits are in)
-  if (kPriv)  // one cell: species sp of the output starts at sp * nodes
-    for (int i = threadIdx.x; i < kSpecies * G.nodes; i += blockDim.x)
-      if (f64_acc[i] != 0.0) atomicAdd(A.A + i, f64_acc[i]);
+  for (int i = threadIdx.x; i < n_out; i += blockDim.x)  // kPriv: the same layout as the output
+    if (f64_acc[i] != 0.0) atomicAdd(A.A + i, f64_acc[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1443,9 +1442,9 @@ hipError_t launch_collide_f64(const CollideArgs& a, hipStream_t stream) {
   long long blocks = (items * kWave + threads - 1) / threads;
   if (blocks > 4096) blocks = 4096;  // 16 waves per CU; the rest by the grid-stride loop
   if (blocks < 1) blocks = 1;
-  // one cell whose 7 species fit in the default dynamic LDS: workgroup-private deposits
-  const size_t priv_b = (size_t)kSpecies * a.G.nodes * sizeof(double);
-  const bool priv = a.symmetric && a.G.cells == 1 && priv_b <= 65536;
+  // a whole output that fits in the default dynamic LDS: workgroup-private deposits
+  const size_t priv_b = (size_t)kSpecies * a.G.cells * a.G.nodes * sizeof(double);
+  const bool priv = a.symmetric && priv_b <= 65536;
   const dim3 grid((unsigned)blocks), block(threads);
   if (priv) {
     if (a.learned) hipLaunchKernelGGL(HIP_KERNEL_NAME(collide_f64_kernel<true, true>), grid, block, priv_b, stream, a);

@@ -816,9 +816,12 @@ constexpr double kRootNorm = 1.0 / (32.0 * kPi * kPi * kPi * kPi * kPi * 16.0);
 constexpr int kRootWaves = 4;      // wavefronts per workgroup of the root kernel
 constexpr int kRootQueueLen = 128;  // queued samples per wavefront (< 64 left + 64 new)
 
-template <bool kAlt>
+template <bool kAlt, bool kPriv>
 __global__ __launch_bounds__(kRootWaves * kWave) void collide_roots_kernel(CollideArgs A) {
   const Grid& G = A.G;
+  extern __shared__ double root_acc[];  // kPriv: [7][cells][nodes], as the output (see the FP64 kernel)
+  const int n_out = kPriv ? kSpecies * G.cells * G.nodes : 0;
+  for (int i = threadIdx.x; i < n_out; i += blockDim.x) root_acc[i] = 0.0;
   __shared__ unsigned long long blk_ok;
   __shared__ double blk_mc[2];
   __shared__ double blk_var[kMaxChannels];
@@ -923,7 +926,16 @@ __global__ __launch_bounds__(kRootWaves * kWave) void collide_roots_kernel(Colli
         const double vs = fabs(wnb) * (gain + loss);
         vsample += v;
         ssum += vs;
-        if (A.symmetric) {
+        if (kPriv) {
+          deposit<double, double, __HIP_MEMORY_SCOPE_WORKGROUP>(root_acc + (Ac[1] - A.A), s2, v, G.ox, G.oy);
+          deposit<double, double, __HIP_MEMORY_SCOPE_WORKGROUP>(root_acc + (Ac[2] - A.A), s3, -v, G.ox, G.oy);
+          deposit<double, double, __HIP_MEMORY_SCOPE_WORKGROUP>(root_acc + (Ac[3] - A.A), s4, -v, G.ox, G.oy);
+          if (A.scale) {
+            deposit<double, double>(Sc[1], s2, vs, G.ox, G.oy);
+            deposit<double, double>(Sc[2], s3, vs, G.ox, G.oy);
+            deposit<double, double>(Sc[3], s4, vs, G.ox, G.oy);
+          }
+        } else if (A.symmetric) {
           deposit<double, double>(Ac[1], s2, v, G.ox, G.oy);
           deposit<double, double>(Ac[2], s3, -v, G.ox, G.oy);
           deposit<double, double>(Ac[3], s4, -v, G.ox, G.oy);
@@ -1026,7 +1038,9 @@ __global__ __launch_bounds__(kRootWaves * kWave) void collide_roots_kernel(Colli
       if (A.items) A.items[((size_t)cell * A.n_channels + ci) * G.nodes + p1_lin] = dsum;
     }
   }
-  blk.flush(A);
+  blk.flush(A);  // (begins with a barrier: every wave's deposits are in)
+  for (int i = threadIdx.x; i < n_out; i += blockDim.x)
+    if (root_acc[i] != 0.0) atomicAdd(A.A + i, root_acc[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1429,10 +1443,17 @@ hipError_t launch_collide_roots(const CollideArgs& a, bool alt, hipStream_t stre
   long long blocks = (items * kWave + threads - 1) / threads;
   if (blocks > 4096) blocks = 4096;  // 16 waves per CU; the rest by the grid-stride loop
   if (blocks < 1) blocks = 1;
-  if (alt)
-    hipLaunchKernelGGL(collide_roots_kernel<true>, dim3((unsigned)blocks), dim3(threads), 0, stream, a);
-  else
-    hipLaunchKernelGGL(collide_roots_kernel<false>, dim3((unsigned)blocks), dim3(threads), 0, stream, a);
+  // a whole output that fits in 64 KB of dynamic LDS: workgroup-private deposits
+  const size_t priv_b = (size_t)kSpecies * a.G.cells * a.G.nodes * sizeof(double);
+  const bool priv = a.symmetric && priv_b <= 65536;
+  const dim3 grid((unsigned)blocks), block(threads);
+  if (priv) {
+    if (alt) hipLaunchKernelGGL(HIP_KERNEL_NAME(collide_roots_kernel<true, true>), grid, block, priv_b, stream, a);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(collide_roots_kernel<false, true>), grid, block, priv_b, stream, a);
+  } else {
+    if (alt) hipLaunchKernelGGL(HIP_KERNEL_NAME(collide_roots_kernel<true, false>), grid, block, 0, stream, a);
+    else hipLaunchKernelGGL(HIP_KERNEL_NAME(collide_roots_kernel<false, false>), grid, block, 0, stream, a);
+  }
   return hipGetLastError();
 }
 

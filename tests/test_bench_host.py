@@ -1,0 +1,45 @@
+"""Host-side checks of bench.py (no GPU): the one-GPU refusal, the slot
+counts the roofline uses, and that the committed HBM-traffic figure is only
+reported for the kernel sources it was measured on."""
+import importlib.util
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bench():
+    spec = importlib.util.spec_from_file_location("bench_host", os.path.join(ROOT, "bench.py"))
+    b = importlib.util.module_from_spec(spec)
+    argv = sys.argv
+    try:
+        sys.argv = ["bench.py"]
+        spec.loader.exec_module(b)
+    finally:
+        sys.argv = argv
+    return b
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_slot_counts_match_the_tabulated_parts():
+    b = _bench()
+    assert b.SLOTS_REJECTED == 270 and b.SLOTS_ACCEPTED == 519
+    assert b.SLOTS_LEARNED_EXTRA == 440
+    assert b.SLOTS_ROOTS_SAMPLE == 209 and b.SLOTS_ROOTS_ACCEPTED == 224 and b.SLOTS_DEPOSITS == 66
+
+
+def test_traffic_reported_only_for_the_measured_sources():
+    b = _bench()
+    digest = b.kernel_sources_digest()
+    assert len(digest) == 64
+    t = b.measured_traffic("gg_16x16x1_20cube_f32")
+    # the committed counters were taken on these sources: a figure of the right size
+    assert t is not None and 5e7 < t < 1e9
+    assert b.measured_traffic("no_such_workload") is None

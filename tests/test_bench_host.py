@@ -39,7 +39,12 @@ def test_traffic_reported_only_for_the_measured_sources():
     b = _bench()
     digest = b.kernel_sources_digest()
     assert len(digest) == 64
+    prof = open(os.path.join(ROOT, "profiles", "collide_f32_gg_16x16x1_20cube_pmc.md")).read()
+    recorded = [l.split(":", 1)[1].strip() for l in prof.splitlines() if l.startswith("sources_sha256:")]
+    assert len(recorded) == 1
     t = b.measured_traffic("gg_16x16x1_20cube_f32")
-    # the committed counters were taken on these sources: a figure of the right size
-    assert t is not None and 5e7 < t < 1e9
+    if recorded[0] == digest:      # counters taken on these sources: a figure of the right size
+        assert t is not None and 5e7 < t < 1e9
+    else:                          # sources changed since: no stale figure
+        assert t is None
     assert b.measured_traffic("no_such_workload") is None

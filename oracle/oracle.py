@@ -110,6 +110,8 @@ def lib():
         _lib.ref_observables.argtypes = [p, p, p, p, p, p]
         _lib.ref_stencil.restype = i32
         _lib.ref_stencil.argtypes = [p, C.c_int64, p, p, p]
+        _lib.ref_sample_uniforms.restype = None
+        _lib.ref_sample_uniforms.argtypes = [u64, u32, u32, u32, u32, u32, p]
     return _lib
 
 
@@ -159,6 +161,13 @@ def philox4x32_10(ctr, key) -> np.ndarray:
     k = np.asarray(key, dtype=np.uint32).copy()
     out = np.zeros(4, dtype=np.uint32)
     lib().ref_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def sample_uniforms(seed: int, step: int, s: int, p1_lin: int, cell: int, code: int) -> np.ndarray:
+    """The five unit-cube variables of one sample of the uniform sampler."""
+    out = np.zeros(5)
+    lib().ref_sample_uniforms(seed, step, s, p1_lin, cell, code, _ptr(out))
     return out
 
 

@@ -607,6 +607,16 @@ static void five_uniforms(const uint32_t x[4], double u[5]) {
   for (int i = 0; i < 5; ++i) u[i] = unif23(v[i]);
 }
 
+/* the five unit-cube variables of sample s of a work item, uniform sampler
+   (CM-angle estimator): block 0 of the item's Philox stream, five 23-bit
+   fields.  Exported for the tests of recorded training rows. */
+void ref_sample_uniforms(uint64_t seed, uint32_t step, uint32_t s, uint32_t p1_lin, uint32_t cell,
+                         uint32_t code, double u_out[5]) {
+  uint32_t x[4];
+  draw_block(seed, step, s, p1_lin, cell, code, 0u, x);
+  five_uniforms(x, u_out);
+}
+
 static double box_volume(const ref_grid* g) {
   return (2.0 * g->p_half[0]) * (2.0 * g->p_half[1]) * (2.0 * g->p_half[2]);
 }

@@ -88,6 +88,13 @@ enum { REF_EST_CM = 0, REF_EST_ROOT = 1, REF_EST_ROOT_K3 = 2 };
 /* Philox4x32-10 block (Salmon et al., SC'11) */
 void ref_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 
+/* the five unit-cube variables of sample s of work item (cell, channel code,
+   p1) under the uniform sampler: Philox block 0 with key (seed_lo32,
+   seed_hi32 + step), counter (s, p1_lin, cell, code << 8), five 23-bit fields
+   mapped to the midpoints of their cells */
+void ref_sample_uniforms(uint64_t seed, uint32_t step, uint32_t s, uint32_t p1_lin, uint32_t cell,
+                         uint32_t code, double u_out[5]);
+
 /* |M|^2 of Table I (summed over all colours and helicities), or the user's
    matrix element of that row (ref_set_matrix_element) */
 double ref_msq(int32_t row, double s, double t, double u, double mg2, double alpha_s);

@@ -466,7 +466,7 @@ void qgbe_destroy(qgbe_ctx* c) {
   {
     MlpState& m = c->mlp;
     void* bufs[] = {m.params, m.m, m.v, m.grad, m.pb, m.X, m.Xb, m.Z1, m.H1b, m.Z2, m.H2b, m.Y, m.dY, m.dYb,
-                    m.dH, m.dZ, m.dZb, m.yw, m.scalars, m.idx};
+                    m.dH, m.dZ, m.dZb, m.yw, m.scalars};
     for (void* b : bufs) (void)hipFree(b);
   }
   for (auto& e : c->ev)
@@ -604,7 +604,9 @@ qgbe_status qgbe_set_matrix_element(qgbe_ctx* c, int32_t row, int32_t n_terms, c
   else c->msq_mask &= ~(1u << row);
   // the table is read by kernels already queued on the stream: wait for them
   HIP_TRY(hipStreamSynchronize(c->stream), "synchronise");
-  HIP_TRY(hipMemcpy(c->d_msq, &c->msq, sizeof(MsqTable), hipMemcpyHostToDevice), "copy matrix elements");
+  HIP_TRY(hipMemcpyAsync(c->d_msq, &c->msq, sizeof(MsqTable), hipMemcpyHostToDevice, c->stream),
+          "copy matrix elements");
+  HIP_TRY(hipStreamSynchronize(c->stream), "synchronise");
   return QGBE_OK;
 }
 

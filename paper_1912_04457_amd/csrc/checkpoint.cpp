@@ -1,6 +1,7 @@
 // Checkpoint and restore of a context's evolving state: f (FP64), the step
 // index (second Philox key word), the lagged masses that the next mass
-// evaluation uses, and the learned proposal (weights, Adam moments, table).
+// evaluation uses, the learned proposal (weights, Adam moments, table) and
+// the user matrix elements that replace rows of Table I.
 //
 // Byte layout (host, native endianness): a fixed header, then the sections the
 // header announces, each a plain array:
@@ -10,6 +11,7 @@
 //   thr        [channels*nodes][K]      uint32   (K > 0)
 //   mu, sigma  [channels*nodes][K][5]   float    (K > 0)
 //   samplers   [channels]               uint8    (K > 0; 0 = uniform fallback)
+//   msq        one MsqTable (the user terms of every row)  (msq_mask != 0)
 #include <hip/hip_runtime.h>
 
 #include <cstring>
@@ -22,6 +24,7 @@ using namespace qgbe;
 namespace {
 
 constexpr char kMagic[8] = {'Q', 'G', 'B', 'E', 'C', 'K', 'P', '1'};
+constexpr uint32_t kVersion = 2;  // 2: user matrix elements
 
 struct Header {
   char magic[8];
@@ -43,7 +46,7 @@ struct Header {
   int32_t K;
   int32_t table_net;
   float table_alpha;
-  int32_t pad;
+  uint32_t msq_mask;  // bit r: Table I row r replaced by the stored user terms
   uint64_t n_field, n_lag, n_params, n_rows, n_chan;
 };
 
@@ -63,6 +66,7 @@ size_t payload_bytes(const Header& h) {
   if (h.has_lag) b += h.n_lag * sizeof(double);
   if (h.has_weights) b += 3 * h.n_params * sizeof(float);
   if (h.K > 0) b += h.n_rows * h.K * (sizeof(uint32_t) + 10 * sizeof(float)) + h.n_chan;
+  if (h.msq_mask) b += sizeof(MsqTable);
   return b;
 }
 
@@ -76,7 +80,7 @@ qgbe_status qgbe_checkpoint(qgbe_ctx* c, void* buf, size_t* bytes) {
   std::memset(&h, 0, sizeof h);
   std::memcpy(h.magic, kMagic, sizeof kMagic);
   h.header_bytes = sizeof(Header);
-  h.version = 1;
+  h.version = kVersion;
   const qgbe_grid_desc& d = c->d;
   for (int a = 0; a < 3; ++a) {
     h.n_x[a] = d.n_x[a];
@@ -100,6 +104,7 @@ qgbe_status qgbe_checkpoint(qgbe_ctx* c, void* buf, size_t* bytes) {
   h.K = c->K;
   h.table_net = c->table_net ? 1 : 0;
   h.table_alpha = c->table_alpha;
+  h.msq_mask = c->msq_mask;
   h.n_field = field_len(c);
   h.n_lag = (uint64_t)kSpecies * c->G.cells;
   h.n_params = kMlpParams;
@@ -138,6 +143,7 @@ qgbe_status qgbe_checkpoint(qgbe_ctx* c, void* buf, size_t* bytes) {
     HIP_TRY(out(c->d_mix_on, h.n_chan), "copy channel samplers");
   }
   HIP_TRY(hipStreamSynchronize(c->stream), "synchronise");
+  if (h.msq_mask) std::memcpy(p, &c->msq, sizeof(MsqTable));
   *bytes = need;
   return QGBE_OK;
 }
@@ -147,13 +153,25 @@ qgbe_status qgbe_restore(qgbe_ctx* c, const void* buf, size_t bytes) {
   if (bytes < sizeof(Header)) return fail(QGBE_EINVAL, "checkpoint truncated");
   Header h;
   std::memcpy(&h, buf, sizeof h);
-  if (std::memcmp(h.magic, kMagic, sizeof kMagic) != 0 || h.header_bytes != sizeof(Header) || h.version != 1)
+  if (std::memcmp(h.magic, kMagic, sizeof kMagic) != 0 || h.header_bytes != sizeof(Header) ||
+      h.version != kVersion)
     return fail(QGBE_EINVAL, "not a checkpoint of this library version");
   if (!same_grid(h, c->d)) return fail(QGBE_EINVAL, "checkpoint belongs to a different grid or configuration");
   if (h.n_field != field_len(c) || h.n_lag != (uint64_t)kSpecies * c->G.cells || h.n_params != kMlpParams ||
       h.n_rows != (uint64_t)c->nch * c->G.nodes || h.n_chan != (uint64_t)c->nch || h.K < 0 || h.K > 16)
     return fail(QGBE_EINVAL, "checkpoint sizes do not match the context");
+  if (h.msq_mask & ~0xFEu) return fail(QGBE_EINVAL, "checkpoint has a bad matrix-element mask");
   if (bytes < sizeof(Header) + payload_bytes(h)) return fail(QGBE_EINVAL, "checkpoint truncated");
+  MsqTable msq{};
+  if (h.msq_mask) {
+    std::memcpy(&msq, static_cast<const char*>(buf) + sizeof(Header) + payload_bytes(h) - sizeof(MsqTable),
+                sizeof(MsqTable));
+    for (int r = 1; r <= 7; ++r) {
+      const int n = ((h.msq_mask >> r) & 1u) ? msq.n[r] : 0;
+      if (n < 0 || n > kMsqMaxTerms || (((h.msq_mask >> r) & 1u) && n == 0))
+        return fail(QGBE_EINVAL, "checkpoint has bad matrix-element terms");
+    }
+  }
   HIP_TRY(hipSetDevice(c->d.device), "hipSetDevice");
   if (h.has_weights) {
     qgbe_status s = qgbe_proposal_set_weights(c, reinterpret_cast<const float*>(
@@ -188,6 +206,13 @@ qgbe_status qgbe_restore(qgbe_ctx* c, const void* buf, size_t bytes) {
     HIP_TRY(in(c->d_sigma, rk * 5 * sizeof(float)), "copy scales");
     HIP_TRY(in(c->d_mix_on, h.n_chan), "copy channel samplers");
   }
+  HIP_TRY(hipStreamSynchronize(c->stream), "synchronise");
+  // the user matrix elements in force when the checkpoint was taken (rows
+  // without user terms evaluate Table I)
+  c->msq = msq;
+  c->msq_mask = h.msq_mask;
+  HIP_TRY(hipMemcpyAsync(c->d_msq, &c->msq, sizeof(MsqTable), hipMemcpyHostToDevice, c->stream),
+          "copy matrix elements");
   HIP_TRY(hipStreamSynchronize(c->stream), "synchronise");
   c->step = h.step;
   c->has_lag = h.has_lag != 0;

@@ -45,7 +45,6 @@ struct MlpState {
   float* yw = nullptr;
   __bf16 *Xb = nullptr, *H1b = nullptr, *H2b = nullptr, *dYb = nullptr, *dZb = nullptr;
   double* scalars = nullptr;   // [0] loss, [1] weight sum
-  int* idx = nullptr;
 };
 
 }  // namespace qgbe

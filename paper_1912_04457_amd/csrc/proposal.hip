@@ -43,7 +43,6 @@ qgbe_status mlp_ensure(qgbe_ctx* c) {
   MA(m.dZb, (size_t)kBatch * kMlpHidden, "mlp dZ bf16");
   MA(m.yw, (size_t)kBatch * (kMixD + 1), "mlp yw");
   MA(m.scalars, 2, "mlp scalars");
-  MA(m.idx, kBatch, "mlp indices");
 #undef MA
   if (s) return s;
   m.ready = true;
@@ -377,7 +376,9 @@ qgbe_status qgbe_proposal_judge(qgbe_ctx* c, int32_t n_pilot, int32_t n_reps, ui
       s = qgbe_collision_term_ex(c, n_pilot, l ? QGBE_SAMPLER_LEARNED : QGBE_SAMPLER_UNIFORM, c->d_A, 1, nullptr, &st);
       if (s) break;
       t_ms[l] += st.t_collide_ms;
-      hipError_t e = hipMemcpy(h.data(), c->d_chan_var, h.size() * sizeof(double), hipMemcpyDeviceToHost);
+      hipError_t e = hipMemcpyAsync(h.data(), c->d_chan_var, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                                    c->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
       if (e != hipSuccess) { s = hip_fail(e, "copy channel variances"); break; }
       for (int k = 0; k < kStripes; ++k)  // the stripes in order
         for (int ci = 0; ci < nch; ++ci) var[l][ci] += h[(size_t)k * nch + ci];
@@ -417,6 +418,13 @@ qgbe_status qgbe_train_proposal(qgbe_ctx* c, const float* rows, int64_t n, const
             "copy rows");
     d_rows = owned;
   }
+  // the epoch's row order goes to the device once per epoch (one copy, waited
+  // for before the host shuffles again); each batch gathers its slice of it
+  int* d_perm = nullptr;
+  if (hipMalloc(&d_perm, (size_t)n * sizeof(int)) != hipSuccess) {
+    if (owned) (void)hipFree(owned);
+    return fail(QGBE_ENOMEM, "row order scratch");
+  }
   std::mt19937_64 rng(cfg->seed);
   std::vector<int> perm((size_t)n);
   std::iota(perm.begin(), perm.end(), 0);
@@ -426,12 +434,13 @@ qgbe_status qgbe_train_proposal(qgbe_ctx* c, const float* rows, int64_t n, const
   hipError_t e = hipSuccess;
   for (int ep = 0; ep < cfg->epochs && !s && e == hipSuccess; ++ep) {
     std::shuffle(perm.begin(), perm.end(), rng);
-    e = hipMemsetAsync(m.scalars, 0, sizeof(double), c->stream);
+    e = hipMemcpyAsync(d_perm, perm.data(), (size_t)n * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(m.scalars, 0, sizeof(double), c->stream);
     for (int b = 0; b < steps_per_epoch && !s && e == hipSuccess; ++b, ++step) {
       const int r0 = b * cfg->batch;
       const int nr = (int)std::min<int64_t>(cfg->batch, n - r0);
-      e = hipMemcpyAsync(m.idx, perm.data() + r0, nr * sizeof(int), hipMemcpyHostToDevice, c->stream);
-      if (e == hipSuccess) e = launch_gather(d_rows, m.idx, nr, m.X, m.Xb, m.yw, c->stream);
+      e = launch_gather(d_rows, d_perm + r0, nr, m.X, m.Xb, m.yw, c->stream);
       if (e != hipSuccess) break;
       s = loss_grad_staged(c, nr);
       if (s) break;
@@ -447,7 +456,10 @@ qgbe_status qgbe_train_proposal(qgbe_ctx* c, const float* rows, int64_t n, const
       epoch_loss[ep] = tot / steps_per_epoch;
     }
   }
-  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  // wait for the queued work before the scratch buffers go (also after an error)
+  const hipError_t e_sync = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = e_sync;
+  (void)hipFree(d_perm);
   if (owned) (void)hipFree(owned);
   if (s) return s;
   if (e != hipSuccess) return hip_fail(e, "train proposal");

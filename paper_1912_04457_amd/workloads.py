@@ -173,6 +173,20 @@ def smooth_f(cells: int, n_p, p_half, species_mask: int = ALL_SPECIES, amp_g: fl
     return f
 
 
+def cell_varied_f(seed: int, n_x, n_p, p_half, x_half, species_mask: int = ALL_SPECIES) -> np.ndarray:
+    """Smooth momentum profiles (smooth_f) whose amplitude varies from cell to
+    cell: a seeded random factor in [0.4, 1.2] per (species, cell) times a
+    gradient along x, so that neighbouring cells differ in f and in their
+    thermal masses (a spatial force in the drift)."""
+    cells = int(np.prod(n_x))
+    f = smooth_f(cells, n_p, p_half, species_mask=species_mask)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    X = cell_centres(n_x, x_half)
+    tilt = 1.0 + 0.3 * X[:, 0] / max(x_half[0], 1e-300)
+    f *= rng.uniform(0.4, 1.2, size=(7, cells))[:, :, None] * tilt[None, :, None]
+    return f
+
+
 def random_mog_table(seed: int, rows: int, K: int = 8, alpha: float = 0.1,
                      mu_scale: float = 1.5, log_sigma=(-1.0, 0.7)):
     """Random mixture table in the proposal-table format.

@@ -84,3 +84,25 @@ def test_restore_rejects_foreign_or_damaged_buffers():
     with _solver(precision=qgbe.FP32) as c:
         with pytest.raises(qgbe.QgbeError):
             qgbe.qgbe_restore(c.ctx, state)
+
+
+def test_user_matrix_elements_round_trip():
+    """A context restored from a checkpoint taken with a user row of Table I
+    evaluates that row (not Table I) and gives the original's collision term;
+    a context that had its own user rows returns to the checkpoint's."""
+    _case("checkpoint user matrix elements")
+    user7 = [(2000.0, (0, 0, 0, 0, 0, 0)), (-900.0, (1, 0, 1, 2, 0, 0))]
+    f0 = W.random_f(44, WL.cells, WL.nodes) * 0.4
+    with _solver(precision=qgbe.FP64) as a:
+        qgbe.qgbe_set_matrix_element(a.ctx, 7, user7)
+        a.set_f(f0)
+        state = qgbe.qgbe_checkpoint(a.ctx)
+        A_user = a.collision(32)[0]
+        qgbe.qgbe_set_matrix_element(a.ctx, 7, [])
+        A_table = a.collision(32)[0]
+    assert np.abs(A_user - A_table).max() > 1e-3 * np.abs(A_table).max()
+    with _solver(precision=qgbe.FP64) as b:
+        qgbe.qgbe_set_matrix_element(b.ctx, 4, [(5.0, (0, 0, 0, 0, 0, 0))])
+        qgbe.qgbe_restore(b.ctx, state)
+        A_b = b.collision(32)[0]
+    assert np.abs(A_b - A_user).max() <= 1e-12 * np.abs(A_user).max()

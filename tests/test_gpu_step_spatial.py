@@ -1,0 +1,71 @@
+"""GPU step parity on a spatial grid with at least three cells on every axis.
+
+The drift of Eq. left handside (flux form, periodic) has two parts: advection
+in x with velocity p/E, and advection in p with the force -grad_x E, where
+E = sqrt(p^2 + m^2(x)) carries the cell's thermal mass.  With two cells on an
+axis the +1 and -1 neighbours coincide and the central difference of E (the
+force) vanishes; here every axis has three or more cells and f varies from
+cell to cell, so the masses, hence the force and the momentum-space fluxes,
+differ from zero everywhere.  Three steps of the GPU (thermal masses,
+collision term, drift, Euler update) against three oracle steps from the
+same f, same seed:
+
+  FP64   |f_gpu - f_ref| <= 1e-10 max|f_ref - f0|
+  FP32   |f_gpu - f_ref| <= 1e-4  max|f_ref - f0|   (FP32 integrand; drift FP64)
+
+tests/test_drift_sensitivity.py shows on the CPU that a drift with the x
+neighbours swapped, without the force term or with the momentum neighbours
+swapped moves f by far more than these bounds on this case.
+"""
+import numpy as np
+import pytest
+
+from paper_1912_04457_amd import qgbe
+from paper_1912_04457_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SEED = 0x5EED2019
+TOL = {qgbe.FP64: 1e-10, qgbe.FP32: 1e-4}
+SPATIAL = W.Workload("qg7_3x4x5_6cube", (3, 4, 5), (6, 6, 6), (3.0, 3.0, 3.0), (2.0, 2.0, 2.0),
+                     0x7F, 16, "f64", 3, 0.01)
+
+
+def _case(name):
+    print(f"\n[gpu case] {name}", flush=True)
+
+
+def spatial_f():
+    wl = SPATIAL
+    return W.cell_varied_f(41, wl.n_x, wl.n_p, wl.p_half, wl.x_half)
+
+
+@pytest.mark.parametrize("scheme", ["upwind", "central"])
+@pytest.mark.parametrize("precision", [qgbe.FP64, qgbe.FP32])
+def test_step_parity_spatial(O, scheme, precision):
+    _case(f"spatial 3x4x5 step parity scheme={scheme} precision={precision}")
+    wl = SPATIAL
+    g = O.Grid(n_x=wl.n_x, n_p=wl.n_p, x_half=wl.x_half, p_half=wl.p_half, species_mask=wl.species_mask)
+    f0 = spatial_f()
+    st = O.State(f=f0.copy())
+    ref = [O.step(g, st, wl.dt_fm, wl.n_samples, SEED, scheme=scheme) for _ in range(wl.steps)]
+    drift = qgbe.DRIFT_UPWIND if scheme == "upwind" else qgbe.DRIFT_CENTRAL
+    with qgbe.Solver(n_x=wl.n_x, n_p=wl.n_p, x_half=wl.x_half, p_half=wl.p_half,
+                     species_mask=wl.species_mask, alpha_s=wl.alpha_s, precision=precision,
+                     drift=drift, seed=SEED) as s:
+        s.set_f(f0)
+        stats = s.step(wl.dt_fm, wl.n_samples, n_steps=wl.steps)
+        f_gpu = s.get_f()
+    change = np.abs(st.f - f0).max()
+    err = np.abs(f_gpu - st.f).max()
+    print(f"[spatial] max change {change:.3e}, max |f_gpu - f_ref| {err:.3e} ({err / change:.2e} of it)",
+          flush=True)
+    assert err <= TOL[precision] * change
+    # the masses differ from cell to cell: the force term is live
+    m = ref[0]["mass2"]
+    assert np.ptp(m[6]) > 0.1 * m[6].mean()
+    for a, b in zip(stats, ref):
+        assert a["N_total"] == pytest.approx(b["N_total"], rel=1e-13)
+        assert np.allclose(a["mass2_avg"], b["mass2"].mean(axis=1), rtol=1e-12 if precision == qgbe.FP64 else 1e-5)
+    N0 = O.observables(g, f0, O.masses(g, f0))["N_total"]
+    assert abs(stats[-1]["N_total"] - N0) <= 1e-13 * N0

@@ -269,6 +269,37 @@ qgbe_status qgbe_step(qgbe_ctx* ctx, double dt_fm, int32_t n_samples, int32_t sa
  * Eq. energy momentum tensor), FP64. */
 qgbe_status qgbe_observables(qgbe_ctx* ctx, qgbe_stats* st);
 
+/* ---- collision term without device allocation --------------------------- */
+
+/* Device scratch of qgbe_collision_term_noalloc, in MiB: one statically sized
+ * array per GPU, held until the process ends. */
+#define QGBE_NOALLOC_SCRATCH_MIB 64
+
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the collision term of
+ * qgbe_collision_term on a context freshly made from desc, with f set and the
+ * step index at `step`, computed without a context and without any device
+ * allocation.  Masses come from f with E = |p| (the first-call rule), or
+ * desc->const_mass2 with QGBE_MASS_CONSTANT; Table I matrix elements.
+ * f: [7][cells][nodes] float64 on desc->device (read only); A:
+ * [7][cells][nodes] float64 on the same device, overwritten.  Both are owned
+ * by the caller and must stay alive until desc->stream has finished the work.
+ * sampler: QGBE_SAMPLER_UNIFORM (in desc->precision) or one of the root
+ * samplers (FP64); QGBE_SAMPLER_LEARNED is refused (no proposal table).
+ * Everything else the kernels need (channel table, masses, per-launch totals,
+ * the FP32 copy of f and its node quads) lives in one device array of
+ * QGBE_NOALLOC_SCRATCH_MIB MiB per GPU; a grid that needs more returns
+ * QGBE_EINVAL before any device work.  Every call on a GPU shares that GPU's
+ * array, so calls that overlap on one GPU (other streams, other threads)
+ * race; calls in sequence on one stream do not.  Asynchronous on desc->stream
+ * except that the first call, and any call whose channel table differs from
+ * the previous call's, waits for its upload of the table.  No statistics. */
+qgbe_status qgbe_collision_term_noalloc(const qgbe_grid_desc* desc, const double* f, uint32_t step,
+                                        int32_t n_samples, int32_t sampler, double* A);
+
+/* Bytes of the array qgbe_collision_term_noalloc works in. */
+size_t qgbe_noalloc_scratch_bytes(void);
+
 /* ---- proposal table for the learned sampler ------------------------------ */
 
 /* Install a mixture-of-logistic-normals proposal over the five unit-cube

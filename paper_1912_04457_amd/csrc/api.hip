@@ -76,9 +76,6 @@ CollideArgs base_args(qgbe_ctx* c, int n_samples, double* A, double* scale, doub
   return a;
 }
 
-}  // namespace qgbe
-
-namespace {
 
 qgbe_status validate(const qgbe_grid_desc* d) {
   if (!d) return fail(QGBE_EINVAL, "descriptor is NULL");
@@ -252,6 +249,10 @@ qgbe_status run_collide(qgbe_ctx* c, int n_samples, int sampler, double* A, doub
   }
   return QGBE_OK;
 }
+
+}  // namespace qgbe
+
+namespace {
 
 void fill_stats(qgbe_ctx* c, const double* obs, const double* mass2_host, qgbe_stats* st) {
   std::memset(st, 0, sizeof *st);

@@ -101,6 +101,15 @@ struct qgbe_ctx {
 namespace qgbe {
 
 size_t field_len(const qgbe_ctx* c);
+// Descriptor checks (QGBE_EINVAL with a message), the grid it describes, and
+// the LDS plan of the FP32 channel groups (needs c->G, c->d, c->chans and the
+// LDS budgets).
+qgbe_status validate(const qgbe_grid_desc* d);
+void make_grid(const qgbe_grid_desc* d, Grid& G);
+void plan_groups(qgbe_ctx* c);
+// Enqueue the collision kernels of one collision term, accumulating into A
+// (zeroed by the caller); zeroes the per-launch totals first.
+qgbe_status run_collide(qgbe_ctx* c, int n_samples, int sampler, double* A, double* scale, double* items);
 qgbe_status compute_masses(qgbe_ctx* c);
 CollideArgs base_args(qgbe_ctx* c, int n_samples, double* A, double* scale, double* items);
 // Enqueue features, network forward and table construction for the current

@@ -32,7 +32,8 @@ EXPORTS = (
     "qgbe_proposal_get_weights", "qgbe_mlp_forward", "qgbe_mlp_loss_grad", "qgbe_proposal_features",
     "qgbe_record_samples", "qgbe_train_proposal", "qgbe_proposal_build_table", "qgbe_get_proposal_table",
     "qgbe_checkpoint", "qgbe_restore", "qgbe_set_channel_samplers", "qgbe_get_channel_samplers",
-    "qgbe_proposal_judge", "qgbe_set_matrix_element",
+    "qgbe_proposal_judge", "qgbe_set_matrix_element", "qgbe_collision_term_noalloc",
+    "qgbe_noalloc_scratch_bytes",
 )
 MLP_PARAMS = 29016
 MLP_BATCH = 16384
@@ -130,6 +131,8 @@ def lib() -> C.CDLL:
             "qgbe_get_channel_samplers": (i32, [p, p]),
             "qgbe_proposal_judge": (i32, [p, i32, i32, p, p]),
             "qgbe_set_matrix_element": (i32, [p, i32, i32, p, p]),
+            "qgbe_collision_term_noalloc": (i32, [p, p, u32, i32, i32, p]),
+            "qgbe_noalloc_scratch_bytes": (C.c_size_t, []),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -245,6 +248,19 @@ def qgbe_collision_term_ex(ctx, n_samples: int, sampler: int, A_out, scale=None,
     ex = CollideExtras(sp, ip, sdev if scale is not None else idev)
     _check(lib().qgbe_collision_term_ex(ctx, n_samples, sampler, ptr, dev, C.byref(ex),
                                         None if stats is None else C.byref(stats)))
+
+
+def qgbe_collision_term_noalloc(desc: GridDesc, f, step: int, n_samples: int, sampler: int, A) -> None:
+    """f and A: device buffers (torch tensors on desc.device)."""
+    fp, fdev = _arg(f, np.float64)
+    ap, adev = _arg(A, np.float64)
+    if not (fdev and adev):
+        raise ValueError("f and A must be device buffers")
+    _check(lib().qgbe_collision_term_noalloc(C.byref(desc), fp, step, n_samples, sampler, ap))
+
+
+def qgbe_noalloc_scratch_bytes() -> int:
+    return int(lib().qgbe_noalloc_scratch_bytes())
 
 
 def qgbe_step(ctx, dt_fm: float, n_samples: int, sampler: int, n_steps: int, per_step=None) -> None:

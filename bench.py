@@ -55,10 +55,11 @@ SLOTS_ROOTS_ACCEPTED = 10 + 9 + 6 + 24 + 27 + 8 + 123 + 17
 SLOTS_DEPOSITS = 66
 # MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = one full-rate lane op per slot
 ALU_PEAK_SLOTS = 256 * 64 * 2.4e9
-# LDS: 128 B/clk/CU -> 32 four-byte lane accesses per clock per CU
-LDS_PEAK = 256 * 32 * 2.4e9
-LDS_PER_ACCEPTED = 24 + 24     # 3 x 8 gathers, 3 x 8 atomic adds
 HBM_PEAK = 8.0e12               # bytes/s
+# Timed steps by default: about a minute of the GPU for the 7-species spatial
+# workload (its 50-step run is reported separately), the configured count for
+# the others.
+DEFAULT_STEPS = {W.C5.name: 8}
 
 
 # HBM traffic of the collision kernel from rocprofv3 counters, valid only for
@@ -95,14 +96,15 @@ def measured_traffic(workload: str):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default=W.C2.name, choices=sorted(W.WORKLOADS))
+    ap.add_argument("--steps", type=int, default=0, help="timed steps (0: the workload's default)")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default=W.C5.name, choices=sorted(W.WORKLOADS))
     ap.add_argument("--samples", type=int, default=0, help="override samples per point")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB before timing (counter calibration)")
+    ap.add_argument("--no-sub", action="store_true", help="skip the pure-gluon spatial sub-record")
     ap.add_argument("--no-fixed-error", action="store_true",
                     help="skip the plain-vs-learned time per step at fixed MC error")
     ap.add_argument("--replicas", type=int, default=8)
@@ -254,8 +256,10 @@ def fixed_error(R, epochs):
     return out
 
 
-def cpu_baseline(wl, f, n_samples, budget_s):
-    """The FP64 oracle on the first cells of the same workload (collision term)."""
+def cpu_baseline(wl, f, n_samples, budget_s, table=None):
+    """The FP64 oracle on the first cells of the same workload (collision term,
+    the same sampler: for the learned one, the proposal table and per-channel
+    sampler choice the GPU's timed steps started from)."""
     from oracle import oracle as O
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     total_evals, total_t, cells_done = 0.0, 0.0, 0
@@ -268,9 +272,14 @@ def cpu_baseline(wl, f, n_samples, budget_s):
         fs = np.ascontiguousarray(f[:, cells_done:cells_done + k])
         t0 = time.perf_counter()
         m = O.masses(g, fs)
-        O.collision(g, fs, m, W.PHILOX_SEED, 0, n_samples, want_scale=False, threads=threads,
-                    estimator={"roots": "root", "roots_alt": "root_k3"}.get(wl.sampler, "cm"),
-                    symmetric=wl.symmetric)
+        if table is not None:
+            thr, mu, sg, flags = table
+            O.collision_learned(g, fs, m, W.PHILOX_SEED, 0, n_samples, thr, mu, sg, chan_learned=flags,
+                                want_scale=False, threads=threads)
+        else:
+            O.collision(g, fs, m, W.PHILOX_SEED, 0, n_samples, want_scale=False, threads=threads,
+                        estimator={"roots": "root", "roots_alt": "root_k3"}.get(wl.sampler, "cm"),
+                        symmetric=wl.symmetric)
         dt = time.perf_counter() - t0
         total_t += dt
         total_evals += k * nch * wl.nodes * n_samples
@@ -280,9 +289,84 @@ def cpu_baseline(wl, f, n_samples, budget_s):
         per_cell = total_t / cells_done
         k = max(1, int((budget_s - total_t) / per_cell))
     return dict(value=total_evals / total_t, unit="evals/s", cores=threads, kind="oracle",
-                sample=f"collision term of {cells_done} of {wl.cells} cells x {wl.nodes} nodes x "
-                       f"{nch} channel(s) x {n_samples} samples ({total_evals:.3g} evals, "
+                sample=f"collision term ({wl.sampler} sampler) of {cells_done} of {wl.cells} cells x "
+                       f"{wl.nodes} nodes x {nch} channel(s) x {n_samples} samples ({total_evals:.3g} evals, "
                        f"{total_t:.1f} s, FP64, OpenMP)")
+
+
+def run_workload(wl, N, steps, warmup, train_epochs):
+    """Time `steps` steps of a workload after `warmup` untimed ones; the learned
+    sampler is trained first (outside the timed region).  Returns the fields of
+    a bench record and the solver's proposal table (learned runs) for the CPU
+    baseline."""
+    import torch
+    f0 = W.initial_f(wl)
+    prec = qgbe.FP64 if wl.precision == "f64" else qgbe.FP32
+    drift = qgbe.DRIFT_UPWIND if wl.drift == "upwind" else qgbe.DRIFT_CENTRAL
+    solver = qgbe.Solver(n_x=wl.n_x, n_p=wl.n_p, x_half=wl.x_half, p_half=wl.p_half,
+                         species_mask=wl.species_mask, alpha_s=wl.alpha_s, precision=prec,
+                         drift=drift, seed=W.PHILOX_SEED, device=0, symmetric=int(wl.symmetric))
+    solver.set_f(f0)
+    sampler = {"uniform": qgbe.SAMPLER_UNIFORM, "learned": qgbe.SAMPLER_LEARNED, "roots": qgbe.SAMPLER_ROOTS,
+               "roots_alt": qgbe.SAMPLER_ROOTS_ALT}[wl.sampler]
+    roots = sampler in (qgbe.SAMPLER_ROOTS, qgbe.SAMPLER_ROOTS_ALT)
+    prep, table = None, None
+    if sampler == qgbe.SAMPLER_LEARNED:
+        prep = train_proposal(solver, wl, train_epochs)
+    if warmup:
+        solver.step(wl.dt_fm, N, n_steps=warmup, sampler=sampler)
+    if sampler == qgbe.SAMPLER_LEARNED:   # the table the timed steps start from (CPU baseline input)
+        rows = solver.n_channels * wl.nodes
+        table = qgbe.qgbe_get_proposal_table(solver.ctx, rows) + (
+            qgbe.qgbe_get_channel_samplers(solver.ctx, solver.n_channels),)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = solver.step(wl.dt_fm, N, n_steps=steps, sampler=sampler)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    solver.close()
+
+    evals = sum(s["n_evals"] for s in stats)
+    accepted = sum(s["n_accepted"] for s in stats)
+    t_coll = np.array([s["t_collide_ms"] for s in stats]) * 1e-3
+    if roots:   # accepted counts the roots that passed
+        slots = SLOTS_ROOTS_SAMPLE * evals + (SLOTS_ROOTS_ACCEPTED + SLOTS_DEPOSITS * wl.symmetric) * accepted
+    else:
+        slots = SLOTS_ACCEPTED * accepted + SLOTS_REJECTED * (evals - accepted)
+        if not wl.symmetric:
+            slots -= SLOTS_DEPOSITS * accepted
+    if sampler == qgbe.SAMPLER_LEARNED:
+        slots += SLOTS_LEARNED_EXTRA * evals
+    achieved = slots / t_coll.sum()
+    traffic = measured_traffic(wl.name) if N == wl.n_samples else None
+    roof = dict(bound="alu", achieved=achieved, peak=ALU_PEAK_SLOTS, unit="lane-op slots/s",
+                frac=achieved / ALU_PEAK_SLOTS,
+                traffic=traffic,
+                kernel="collide_roots_kernel" if roots else
+                ("collide_f32_kernel" if prec == qgbe.FP32 else "collide_f64_kernel"),
+                kernel_ms_avg=float(t_coll.mean() * 1e3),
+                hbm_frac=None if traffic is None else traffic / float(t_coll.mean()) / HBM_PEAK)
+    N0, E0 = stats[0]["N_total"], stats[0]["E_total"]
+    rec = {
+        "value": evals / elapsed, "steps": steps, "warmup": warmup, "ms_per_step": elapsed / steps * 1e3,
+        "dtype": "f32" if prec == qgbe.FP32 else "f64",
+        "config": {"workload": wl.name, "cells": wl.cells, "momentum_nodes": wl.nodes,
+                   "species_mask": wl.species_mask, "channels": solver.n_channels,
+                   "samples_per_point": N, "sampler": wl.sampler, "symmetric": wl.symmetric,
+                   "precision": "fp32 integrand, fp64 geometry + accumulation" if prec == qgbe.FP32
+                   else "fp64", "drift": wl.drift, "dt_fm": wl.dt_fm},
+        "roofline": roof,
+        "accepted_fraction": accepted / evals,
+        "collide_ms_per_step": float(t_coll.mean() * 1e3),
+        # particle number over the timed steps (symmetric sampling and the flux-form drift
+        # conserve it to rounding); the kinetic energy changes with the dynamic masses
+        "N_total_rel_drift": abs(stats[-1]["N_total"] - N0) / N0,
+        "E_total_rel_change": (stats[-1]["E_total"] - E0) / E0,
+        "mc_err_est": float(np.mean([s["mc_err_est"] for s in stats])),
+    }
+    if prep is not None:
+        rec["proposal"] = prep
+    return rec, f0, table
 
 
 def main():
@@ -301,73 +385,21 @@ def main():
         del src, dst
     wl = W.WORKLOADS[a.workload]
     N = a.samples or wl.n_samples
-    f0 = W.initial_f(wl)
-    prec = qgbe.FP64 if wl.precision == "f64" else qgbe.FP32
-    drift = qgbe.DRIFT_UPWIND if wl.drift == "upwind" else qgbe.DRIFT_CENTRAL
-    solver = qgbe.Solver(n_x=wl.n_x, n_p=wl.n_p, x_half=wl.x_half, p_half=wl.p_half,
-                         species_mask=wl.species_mask, alpha_s=wl.alpha_s, precision=prec,
-                         drift=drift, seed=W.PHILOX_SEED, device=0, symmetric=int(wl.symmetric))
-    solver.set_f(f0)
-    sampler = {"uniform": qgbe.SAMPLER_UNIFORM, "learned": qgbe.SAMPLER_LEARNED, "roots": qgbe.SAMPLER_ROOTS,
-               "roots_alt": qgbe.SAMPLER_ROOTS_ALT}[wl.sampler]
-    roots = sampler in (qgbe.SAMPLER_ROOTS, qgbe.SAMPLER_ROOTS_ALT)
-    prep = None
-    if sampler == qgbe.SAMPLER_LEARNED:
-        prep = train_proposal(solver, wl, a.train_epochs)
-    if a.warmup:
-        solver.step(wl.dt_fm, N, n_steps=a.warmup, sampler=sampler)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    stats = solver.step(wl.dt_fm, N, n_steps=a.steps, sampler=sampler)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    solver.close()
-
-    evals = sum(s["n_evals"] for s in stats)
-    accepted = sum(s["n_accepted"] for s in stats)
-    t_coll = np.array([s["t_collide_ms"] for s in stats]) * 1e-3
-    value = evals / elapsed
-    if roots:   # accepted counts the roots that passed
-        slots = SLOTS_ROOTS_SAMPLE * evals + (SLOTS_ROOTS_ACCEPTED + SLOTS_DEPOSITS * wl.symmetric) * accepted
-    else:
-        slots = SLOTS_ACCEPTED * accepted + SLOTS_REJECTED * (evals - accepted)
-        if not wl.symmetric:
-            slots -= SLOTS_DEPOSITS * accepted
-    if sampler == qgbe.SAMPLER_LEARNED:
-        slots += SLOTS_LEARNED_EXTRA * evals
-    achieved = slots / t_coll.sum()
-    traffic = measured_traffic(wl.name) if a.samples in (0, wl.n_samples) else None
-    roof = dict(bound="alu", achieved=achieved, peak=ALU_PEAK_SLOTS, unit="lane-op slots/s",
-                frac=achieved / ALU_PEAK_SLOTS,
-                traffic=traffic,
-                kernel="collide_roots_kernel" if roots else
-                ("collide_f32_kernel" if prec == qgbe.FP32 else "collide_f64_kernel"),
-                kernel_ms_avg=float(t_coll.mean() * 1e3),
-                lds_frac=None if roots or prec == qgbe.FP64 else (LDS_PER_ACCEPTED * accepted / t_coll.sum()) / LDS_PEAK,
-                hbm_frac=None if traffic is None else traffic / float(t_coll.mean()) / HBM_PEAK)
-    N0 = stats[0]["N_total"]
-    out = {
-        "metric": METRIC, "value": value, "unit": "evals/s", "n_gpus": 1, "steps": a.steps,
-        "warmup": a.warmup, "ms_per_step": elapsed / a.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if prec == qgbe.FP32 else "f64",
-        "data": "synthetic",
-        "config": {"workload": wl.name, "cells": wl.cells, "momentum_nodes": wl.nodes,
-                   "species_mask": wl.species_mask, "channels": solver.n_channels,
-                   "samples_per_point": N, "sampler": wl.sampler, "symmetric": wl.symmetric,
-                   "precision": "fp32 integrand, fp64 geometry + accumulation" if prec == qgbe.FP32
-                   else "fp64", "drift": wl.drift, "dt_fm": wl.dt_fm},
-        "roofline": roof,
-        "accepted_fraction": accepted / evals,
-        "collide_ms_per_step": float(t_coll.mean() * 1e3),
-        "N_total_rel_drift": abs(stats[-1]["N_total"] - N0) / N0,
-        "mc_err_est": float(np.mean([s["mc_err_est"] for s in stats])),
-    }
-    if prep is not None:
-        out["proposal"] = prep
+    steps = a.steps or DEFAULT_STEPS.get(wl.name, wl.steps)
+    rec, f0, table = run_workload(wl, N, steps, a.warmup, a.train_epochs)
+    out = {"metric": METRIC, "value": rec.pop("value"), "unit": "evals/s", "n_gpus": 1,
+           "steps": rec.pop("steps"), "warmup": rec.pop("warmup"), "ms_per_step": rec.pop("ms_per_step"),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": rec.pop("dtype"),
+           "data": "synthetic"}
+    out.update(rec)
+    if not a.no_sub:
+        # the pure-gluon spatial workload as a sub-record (its own steps)
+        sub, _, _ = run_workload(W.C2, W.C2.n_samples, W.C2.steps, 2, a.train_epochs)
+        out["sub_records"] = {W.C2.name: sub}
     if not a.no_fixed_error:
         out["fixed_mc_error"] = fixed_error(a.replicas, a.train_epochs)
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, f0, N, a.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(wl, f0, N, a.cpu_seconds, table)
     print(json.dumps(out))
 
 

@@ -28,7 +28,12 @@ import numpy as np
 from . import qgbe
 from . import workloads as W
 
-KINDS = {"gluon": 1 << W.GLUON, "quark": (1 << 0) | (1 << 3), "mixture": W.ALL_SPECIES}
+KINDS = {"gluon": 1 << W.GLUON, "quark": (1 << 0) | (1 << 3), "u": 1 << 0, "mixture": W.ALL_SPECIES,
+         "mixture_g": W.ALL_SPECIES}
+# Species that start from the step; the others start empty.  "u" is the
+# paper's pure-quark system (u quarks only, Sec. IV D); "mixture_g" its
+# quark-gluon run, all species evolving from gluons alone (Sec. IV E).
+STARTS = {"mixture_g": 1 << W.GLUON}
 
 
 def initial_step(n_p, p_half, mask: int, f0: float, Qs: float, xi: float = 1.0) -> np.ndarray:
@@ -58,7 +63,7 @@ def evolve(kind: str = "gluon", n_p=(20, 20, 20), p_half=(2.0, 2.0, 2.0), f0: fl
     if steps < 1 or every < 1:
         raise ValueError("steps and every must be >= 1")
     mask = KINDS[kind]
-    f = initial_step(n_p, p_half, mask, f0, Qs, xi)
+    f = initial_step(n_p, p_half, STARTS.get(kind, mask), f0, Qs, xi)
     soft = soft_nodes(n_p, p_half)
     masses = {} if const_mass2 is None else dict(mass_mode=qgbe.MASS_CONSTANT, const_mass2=tuple(const_mass2))
     with qgbe.Solver(n_x=(1, 1, 1), n_p=tuple(n_p), p_half=tuple(p_half), species_mask=mask, alpha_s=alpha_s,

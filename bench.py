@@ -29,30 +29,35 @@ from paper_1912_04457_amd import workloads as W  # noqa: E402
 
 METRIC = "collision integrand evals/s + time/step at fixed MC error, plain vs learned"
 
-# Algorithmic VALU work per evaluation, in lane-issue slots (full-rate op = 1,
-# quarter-rate transcendental or 32-bit integer product = 4):
-#   Philox4x32-10 block 120 (10 rounds x (2 products x 4 + 4 xor)),
-#   five 23-bit uniforms 20, FP64 sample geometry up to the box cut 130
-#   (4 square roots, 3 reciprocals, sin/cos, two boosts, the frame), then for
-#   accepted samples: t and u 16, |M|^2 27 (3 reciprocals), three trilinear
-#   interpolations 123, bracket and value 17, three trilinear deposits 66.
-SLOTS_REJECTED = 120 + 20 + 130
-SLOTS_ACCEPTED = SLOTS_REJECTED + 16 + 27 + 123 + 17 + 66
-# The learned sampler adds per evaluation: a second Philox block 120, the
-# mixture draw 110 (Box-Muller: 3 logs, 3 square roots, 3 sin/cos pairs;
-# 5 logistic maps: 5 exponentials, 5 reciprocals; component choice and
-# y = mu + sigma z), the mixture density 210 (8 components x 5 dimensions x
-# 3 ops, 8 exponentials, 5 log-Jacobian terms, one log).
-SLOTS_LEARNED_EXTRA = 120 + 110 + 210
-# The root parameterisation (FP64, per sample): Philox 120, uniforms 20, the
-# sampled momenta and a 3, the quadratic's coefficients and square root 31,
-# each of its two roots 15 (z, E3, the sign test); per accepted root: the
-# eliminated momentum and its energy 10, J 9, box 6, s, t, u 24, |M|^2 27, the
-# value 8, stencils and interpolations 123, bracket 17, and with symmetric
-# sampling the deposits 66.
-SLOTS_ROOTS_SAMPLE = 120 + 20 + 8 + 31 + 2 * 15
-SLOTS_ROOTS_ACCEPTED = 10 + 9 + 6 + 24 + 27 + 8 + 123 + 17
-SLOTS_DEPOSITS = 66
+# Algorithmic work per evaluation in lane-op issue slots.  The floating-point
+# part is the oracle's per-sample arithmetic as its op-count build counts it
+# (oracle/opcount.cpp: the operations that depend on the sample, each distinct
+# operation once per sample, a multiplication whose only use is an addition
+# fused with it), weighted by issue cost on gfx950: 1 for add, mul, fma,
+# compare and conversion, 4 for a division by a sample-dependent value, a
+# square root and exp/log/sin/cos (one quarter-rate hardware instruction).
+# The integer part follows the definitions: a Philox4x32-10 block is ten rounds
+# of two 32x32->64 products and four xors, 60 slots (the product instruction
+# issues at full rate, measured); five 23-bit uniforms from a block 27 (12
+# shifts, masks and ors, 5 conversions, 5 additions, 5 scalings).
+# tests/test_opcount.py checks these figures against the op-count build.
+PHILOX_BLOCK = 60
+UNIFORMS_FROM_BLOCK = 27
+FP_OUTSIDE_BOX = 179.0      # uniform sampler, sample rejected by the box cut
+FP_ACCEPTED = 388.7         # accepted, symmetric deposits
+FP_DEPOSITS = 21.2          # of which the three symmetric deposits (direct estimator: without)
+FP_MIXTURE = 519.0          # mixture draw (three Box-Muller pairs, five logistic maps) and density
+MIXTURE_INT = 24 + 14       # six more 23-bit uniforms; the component choice (7 compares, 7 selects)
+FP_ROOTS_SAMPLE = 47.3      # root parameterisation: the quadratic and its two candidates
+FP_ROOTS_PER_ROOT = 180.3   # per valid root (direct); with symmetric deposits FP_DEPOSITS more
+SLOTS_REJECTED = PHILOX_BLOCK + UNIFORMS_FROM_BLOCK + FP_OUTSIDE_BOX
+SLOTS_ACCEPTED = PHILOX_BLOCK + UNIFORMS_FROM_BLOCK + FP_ACCEPTED
+SLOTS_DEPOSITS = FP_DEPOSITS
+# the learned sampler: a second Philox block and the mixture draw and density
+# in place of the five uniforms of the plain map
+SLOTS_LEARNED_EXTRA = PHILOX_BLOCK + MIXTURE_INT + FP_MIXTURE - UNIFORMS_FROM_BLOCK
+SLOTS_ROOTS_SAMPLE = PHILOX_BLOCK + UNIFORMS_FROM_BLOCK + FP_ROOTS_SAMPLE
+SLOTS_ROOTS_ACCEPTED = FP_ROOTS_PER_ROOT
 # MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = one full-rate lane op per slot
 ALU_PEAK_SLOTS = 256 * 64 * 2.4e9
 HBM_PEAK = 8.0e12               # bytes/s

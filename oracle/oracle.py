@@ -47,6 +47,27 @@ def build(force: bool = False) -> str:
     return LIB_PATH
 
 
+OPCOUNT_SRC = os.path.join(HERE, "opcount.cpp")
+OPCOUNT_BIN = os.path.join(HERE, "opcount")
+
+
+def build_opcount(force: bool = False) -> str:
+    """Compile the op-count build of the oracle (the same C source with a
+    counting number type; see opcount.cpp) with g++."""
+    deps = [OPCOUNT_SRC, SRC, os.path.join(HERE, "qgbe_oracle.h")]
+    if force or not os.path.exists(OPCOUNT_BIN) or os.path.getmtime(OPCOUNT_BIN) < max(map(os.path.getmtime, deps)):
+        subprocess.check_call(["g++", "-O1", "-std=c++17", "-o", OPCOUNT_BIN + ".tmp", OPCOUNT_SRC, "-lm"])
+        os.replace(OPCOUNT_BIN + ".tmp", OPCOUNT_BIN)
+    return OPCOUNT_BIN
+
+
+def op_counts() -> dict:
+    """Per-sample operation counts of the oracle's estimators, by class (the
+    JSON object opcount.cpp prints)."""
+    import json
+    return json.loads(subprocess.check_output([build_opcount()], text=True))
+
+
 class _Grid(C.Structure):
     _fields_ = [("n_x", C.c_int32 * 3), ("n_p", C.c_int32 * 3),
                 ("x_half", C.c_double * 3), ("p_half", C.c_double * 3),

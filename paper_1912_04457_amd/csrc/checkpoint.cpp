@@ -188,6 +188,9 @@ qgbe_status qgbe_restore(qgbe_ctx* c, const void* buf, size_t bytes) {
     return e;
   };
   HIP_TRY(in(c->d_f, h.n_field * sizeof(double)), "copy f");
+  // the second buffer of f too: a step updates only the evolving species
+  HIP_TRY(hipMemcpyAsync(c->d_f_next, c->d_f, h.n_field * sizeof(double), hipMemcpyDeviceToDevice, c->stream),
+          "copy f to the second buffer");
   HIP_TRY(launch_to_f32(c->d_f, c->d_f32, h.n_field, c->stream), "f to fp32");
   if (h.has_lag) HIP_TRY(in(c->d_lag, h.n_lag * sizeof(double)), "copy lagged masses");
   if (h.has_weights) {

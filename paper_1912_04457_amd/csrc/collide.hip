@@ -1129,13 +1129,13 @@ __device__ __forceinline__ int xcd_local_block(int b, int n) {
 
 // Workgroup size: 12 waves, 3 per SIMD (the register budget is then 168
 // VGPRs; the learned variant spills a few to scratch and still runs faster
-// than with 8 waves).
-constexpr int f32_threads(bool learned) { return learned ? 768 : 768; }
+// than with 8 waves), for both samplers.
+constexpr int kF32Threads = 768;
 // The compacting variant (below) keeps a sample queue per wave in LDS (52 B
 // per entry) next to the accumulators and reads f from the global node quads.
 constexpr int kQueueWaves = 12;
 constexpr int kQueueLen = 128;  // ring entries per wave (>= 63 pending + 64 new)
-constexpr int f32_block(bool learned, bool queue) { return queue ? kQueueWaves * 64 : f32_threads(learned); }
+constexpr int f32_block(bool queue) { return queue ? kQueueWaves * 64 : kF32Threads; }
 
 // kQueue (uniform sampler, every deposit slot in LDS, f from the global node
 // quads): each wave first runs the sample geometry for 64 samples, appends
@@ -1147,14 +1147,14 @@ constexpr int f32_block(bool learned, bool queue) { return queue ? kQueueWaves *
 // LDS works off the atomics behind VALU work.  Same arithmetic per sample as
 // the direct loop.
 template <bool kSym, bool kScale, bool kAllLds, bool kLearned, bool kQueue>
-__global__ __launch_bounds__(f32_block(kLearned, kQueue)) void collide_f32_kernel(CollideArgs A) {
+__global__ __launch_bounds__(f32_block(kQueue)) void collide_f32_kernel(CollideArgs A) {
   static_assert(!kQueue || (kSym && kAllLds && !kLearned), "the queue serves the uniform sampler, slots in LDS");
   // kAllLds: every f tile and accumulator in LDS (the queue variant: every
   // accumulator; f from the quads)
   constexpr bool kTilesLds = kAllLds && !kQueue;
   constexpr bool kAccLds = kAllLds;
   extern __shared__ double lds[];
-  __shared__ float mix_rows[kLearned ? f32_threads(true) / kWave : 1][kLearned ? kMixRow : 1];
+  __shared__ float mix_rows[kLearned ? kF32Threads / kWave : 1][kLearned ? kMixRow : 1];
   __shared__ uint32_t q_v[kQueue ? kQueueWaves : 1][3][kQueue ? kQueueLen : 1];  // 23-bit uniforms of p2
   __shared__ double q_p3[kQueue ? kQueueWaves : 1][3][kQueue ? kQueueLen : 1];
   __shared__ float q_f[kQueue ? kQueueWaves : 1][4][kQueue ? kQueueLen : 1];    // s, t, u, prefactor
@@ -1517,7 +1517,7 @@ void launch_f32_sampler(const CollideArgs& a, bool all_lds, bool queue, dim3 gri
   else launch_f32_variant<kSym, kScale, false>(a, all_lds, queue, grid, block, lds, st);
 }
 
-int collide_f32_waves(bool learned, bool queue) { return f32_block(learned, queue) / kWave; }
+int collide_f32_waves(bool queue) { return f32_block(queue) / kWave; }
 
 hipError_t launch_collide_f32(const CollideArgs& a, int nslot, bool queue, hipStream_t stream) {
   const int n_acc = a.symmetric ? std::min(a.slot_hi - a.slot_lo, a.lds_acc) : 0;
@@ -1527,7 +1527,7 @@ hipError_t launch_collide_f32(const CollideArgs& a, int nslot, bool queue, hipSt
   const bool all_acc = !a.symmetric || n_acc == a.slot_hi - a.slot_lo;
   const bool all_lds = n_tiles == nslot && all_acc;
   queue = queue && all_acc && a.symmetric && !a.learned && a.win_n == a.G.nodes;
-  const int threads = f32_block(a.learned != 0, queue);
+  const int threads = f32_block(queue);
   const size_t lds = (size_t)n_acc * a.win_n * sizeof(double) + (size_t)n_tiles * a.G.nodes * sizeof(float);
   const long long blocks = (long long)a.G.cells * a.n_group * a.n_chunks;
   if (blocks <= 0) return hipSuccess;

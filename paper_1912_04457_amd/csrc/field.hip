@@ -149,22 +149,29 @@ __device__ double drift_at(const Grid& G, const double* f, const double* mass2, 
   return D;
 }
 
-// f_out = f + dt (A / (N_Y hbar c) - D[f]) for evolving species; frozen otherwise.
-__global__ __launch_bounds__(kBlock) void update_kernel(Grid G, const double* __restrict__ f,
+// The evolving species, in order (the update touches only these; the frozen
+// species hold the same values in both buffers of f, set together).
+struct Evolving {
+  int n;
+  int sp[kSpecies];
+};
+
+// f_out = f + dt (A / (N_Y hbar c) - D[f]) for the evolving species.
+__global__ __launch_bounds__(kBlock) void update_kernel(Grid G, Evolving ev, const double* __restrict__ f,
                                                         const double* __restrict__ A,
                                                         const double* __restrict__ mass2, double dt,
                                                         int scheme, double* __restrict__ f_out,
                                                         float* __restrict__ f32) {
-  const size_t total = (size_t)kSpecies * G.cells * G.nodes;
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
-    const int sp = (int)(i / ((size_t)G.cells * G.nodes));
-    const size_t rem = i - (size_t)sp * G.cells * G.nodes;
+  const size_t per = (size_t)G.cells * G.nodes;
+  const size_t total = (size_t)ev.n * per;
+  for (size_t j = blockIdx.x * (size_t)blockDim.x + threadIdx.x; j < total; j += (size_t)gridDim.x * blockDim.x) {
+    const int k = (int)(j / per);
+    const size_t rem = j - (size_t)k * per;
+    const int sp = ev.sp[k];
+    const size_t i = (size_t)sp * per + rem;
     const int cell = (int)(rem / G.nodes), node = (int)(rem % G.nodes);
-    double v = f[i];
-    if ((G.species_mask >> sp) & 1u) {
-      const double D = drift_at(G, f, mass2, sp, cell, node, scheme);
-      v += dt * (A[i] / (degeneracy(sp) * kHbarC) - D);
-    }
+    const double D = drift_at(G, f, mass2, sp, cell, node, scheme);
+    const double v = f[i] + dt * (A[i] / (degeneracy(sp) * kHbarC) - D);
     f_out[i] = v;
     f32[i] = (float)v;
   }
@@ -363,8 +370,13 @@ hipError_t launch_const_masses(const Grid& G, const Mass7& m, double* mass2, hip
 
 hipError_t launch_update(const Grid& G, const double* f, const double* A, const double* mass2, double dt,
                          int scheme, double* f_out, float* f32, hipStream_t st) {
-  const size_t n = (size_t)kSpecies * G.cells * G.nodes;
-  hipLaunchKernelGGL(update_kernel, dim3(grid_for(n)), dim3(kBlock), 0, st, G, f, A, mass2, dt, scheme, f_out, f32);
+  Evolving ev{};
+  for (int sp = 0; sp < kSpecies; ++sp)
+    if ((G.species_mask >> sp) & 1u) ev.sp[ev.n++] = sp;
+  const size_t n = (size_t)ev.n * G.cells * G.nodes;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(update_kernel, dim3(grid_for(n)), dim3(kBlock), 0, st, G, ev, f, A, mass2, dt, scheme, f_out,
+                     f32);
   return hipGetLastError();
 }
 

@@ -68,3 +68,30 @@ def test_smallest_grid_single_sample(O, sampler, precision):
     g, A, S, st, A_ref, S_ref = _pair(O, n_x, n_p, 0x7F, f, 1, precision, sampler)
     tol = TOL[precision] if sampler == qgbe.SAMPLER_UNIFORM else 1e-10
     _check(g, A, A_ref, S_ref, tol)
+
+
+@pytest.mark.parametrize("precision", [qgbe.FP64, qgbe.FP32])
+def test_frozen_species_stay_fixed_across_steps(precision):
+    """A step updates only the evolving species; the others keep their values
+    in both buffers of f, also after one of them is set anew between steps
+    (an odd and an even number of steps after the setting)."""
+    _case(f"frozen species across steps precision={precision}")
+    n_x, n_p = (2, 1, 1), (4, 4, 4)
+    mask = (1 << 0) | (1 << 6)                    # u and g evolve
+    f = W.random_f(53, 2, 64) * 0.4               # every species occupied
+    frozen = [sp for sp in range(7) if not (mask >> sp) & 1]
+    with qgbe.Solver(n_x=n_x, n_p=n_p, x_half=(3.0, 3.0, 3.0), p_half=(2.0, 2.0, 2.0), species_mask=mask,
+                     seed=SEED, precision=precision) as s:
+        s.set_f(f)
+        s.step(0.01, 32, n_steps=3)
+        g1 = s.get_f()
+        assert np.array_equal(g1[frozen], f[frozen])
+        assert not np.array_equal(g1[0], f[0]) and not np.array_equal(g1[6], f[6])
+        f_d = np.full((1, 2, 64), 0.123)
+        s.set_f(f_d, species=1)
+        for n in (1, 2):
+            s.step(0.01, 32, n_steps=n)
+            g2 = s.get_f()
+            assert np.all(g2[1] == 0.123)
+            assert np.array_equal(np.delete(g2[frozen], frozen.index(1), axis=0),
+                                  np.delete(f[frozen], frozen.index(1), axis=0))

@@ -110,6 +110,7 @@ def parse():
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="run one device copy of this many MiB before timing (counter calibration)")
     ap.add_argument("--no-sub", action="store_true", help="skip the pure-gluon spatial sub-record")
+    ap.add_argument("--progress", action="store_true", help="print a line per timed step on stderr")
     ap.add_argument("--no-fixed-error", action="store_true",
                     help="skip the plain-vs-learned time per step at fixed MC error")
     ap.add_argument("--replicas", type=int, default=8)
@@ -299,7 +300,7 @@ def cpu_baseline(wl, f, n_samples, budget_s, table=None):
                        f"{total_t:.1f} s, FP64, OpenMP)")
 
 
-def run_workload(wl, N, steps, warmup, train_epochs):
+def run_workload(wl, N, steps, warmup, train_epochs, progress=False):
     """Time `steps` steps of a workload after `warmup` untimed ones; the learned
     sampler is trained first (outside the timed region).  Returns the fields of
     a bench record and the solver's proposal table (learned runs) for the CPU
@@ -326,9 +327,28 @@ def run_workload(wl, N, steps, warmup, train_epochs):
             qgbe.qgbe_get_channel_samplers(solver.ctx, solver.n_channels),)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    stats = solver.step(wl.dt_fm, N, n_steps=steps, sampler=sampler)
+    if progress:   # one call per step, a line per step on stderr (long runs)
+        stats = []
+        for k in range(steps):
+            stats += solver.step(wl.dt_fm, N, n_steps=1, sampler=sampler)
+            print(f"step {k + 1}/{steps}: {stats[-1]['t_step_ms']:.1f} ms, N {stats[-1]['N_total']:.15g}",
+                  file=sys.stderr, flush=True)
+    else:
+        stats = solver.step(wl.dt_fm, N, n_steps=steps, sampler=sampler)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    compare = None
+    if sampler == qgbe.SAMPLER_LEARNED:
+        # after the timed steps, on the same f: one learned and one plain collision
+        # term with the same samples per point (the learned one from the proposal
+        # table shared by all cells): estimated MC error and kernel time of each
+        compare = {}
+        for name, smp in (("learned", qgbe.SAMPLER_LEARNED), ("plain", qgbe.SAMPLER_UNIFORM)):
+            st = solver.collision(N, sampler=smp)[3]
+            compare[name] = dict(mc_err_est=st.mc_err_est, t_collide_ms=st.t_collide_ms)
+        compare["error_ratio_plain_over_learned"] = compare["plain"]["mc_err_est"] / compare["learned"]["mc_err_est"]
+        compare["variance_time_gain"] = (compare["plain"]["mc_err_est"] ** 2 * compare["plain"]["t_collide_ms"]) / (
+            compare["learned"]["mc_err_est"] ** 2 * compare["learned"]["t_collide_ms"])
     solver.close()
 
     evals = sum(s["n_evals"] for s in stats)
@@ -371,6 +391,8 @@ def run_workload(wl, N, steps, warmup, train_epochs):
     }
     if prep is not None:
         rec["proposal"] = prep
+    if compare is not None:
+        rec["learned_vs_plain_same_samples"] = compare
     return rec, f0, table
 
 
@@ -391,7 +413,7 @@ def main():
     wl = W.WORKLOADS[a.workload]
     N = a.samples or wl.n_samples
     steps = a.steps or DEFAULT_STEPS.get(wl.name, wl.steps)
-    rec, f0, table = run_workload(wl, N, steps, a.warmup, a.train_epochs)
+    rec, f0, table = run_workload(wl, N, steps, a.warmup, a.train_epochs, a.progress)
     out = {"metric": METRIC, "value": rec.pop("value"), "unit": "evals/s", "n_gpus": 1,
            "steps": rec.pop("steps"), "warmup": rec.pop("warmup"), "ms_per_step": rec.pop("ms_per_step"),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": rec.pop("dtype"),

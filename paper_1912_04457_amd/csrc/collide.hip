@@ -539,13 +539,24 @@ __device__ __forceinline__ void mix_prepare_f32(const uint32_t* thr, const float
     row[40 + i] = (float)rcp64((double)sg[i]);
     row[kMixSigma + i] = sg[i];
   }
-  if (lane < K) {
-    const double hi = lane + 1 < K ? (double)thr[lane + 1] : kTwo32;
-    const double pk = (hi - (double)thr[lane]) * (1.0 / kTwo32);
-    double c = pk > 0.0 ? log64(pk) - 5.0 * kHalfLog2Pi : -1e30;
-    for (int d = 0; d < 5; ++d) c -= log64((double)sg[lane * 5 + d]);
-    row[80 + lane] = (float)c;
+  // log pi_k - sum_d log sigma_kd - 5/2 log 2pi: the K x 6 logarithms one per
+  // lane (lane 6k holds log pi_k, lanes 6k+1..6k+5 -log sigma_kd), gathered
+  // by lane k; the wave waits for one logarithm instead of six in a row
+  double lg = 0.0;
+  const int kc = lane / 6, jc = lane - 6 * kc;
+  if (lane < 6 * K) {
+    if (jc == 0) {
+      const double hi = kc + 1 < K ? (double)thr[kc + 1] : kTwo32;
+      const double pk = (hi - (double)thr[kc]) * (1.0 / kTwo32);
+      lg = pk > 0.0 ? log64(pk) : -1e30;
+    } else {
+      lg = -log64((double)sg[kc * 5 + jc - 1]);
+    }
   }
+  double c = -5.0 * kHalfLog2Pi;
+#pragma unroll
+  for (int t = 0; t < 6; ++t) c += __shfl(lg, min(6 * lane + t, kWave - 1), kWave);
+  if (lane < K) row[80 + lane] = (float)c;
   if (lane == 0) row[88] = (float)((double)thr[0] / kTwo32);
 }
 
@@ -1352,10 +1363,18 @@ __global__ __launch_bounds__(f32_block(kQueue)) void collide_f32_kernel(CollideA
       evaluate(u, inv_q);
     }
     if (!A.direct) continue;
-    dsum = wave_sum(dsum);
-    if (kScale) ssum = wave_sum(ssum);
-    dsq = wave_sum(dsq);
-    const int ok_total = wave_count(n_ok);
+    int ok_total;
+    if (kLearned) {  // short items (few hundred samples): DPP sums, no LDS round trips
+      dsum = wave_sum_dpp(dsum);
+      if (kScale) ssum = wave_sum_dpp(ssum);
+      dsq = wave_sum_dpp(dsq);
+      ok_total = wave_count_dpp(n_ok);
+    } else {
+      dsum = wave_sum(dsum);
+      if (kScale) ssum = wave_sum(ssum);
+      dsq = wave_sum(dsq);
+      ok_total = wave_count(n_ok);
+    }
     if (lane == 0) {
       __hip_atomic_fetch_add(&ok_wg, (unsigned long long)ok_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       __hip_atomic_fetch_add(&mc_wg[0], item_variance(dsum, dsq, A.n_samples), __ATOMIC_RELAXED,

@@ -67,9 +67,13 @@ HBM_PEAK = 8.0e12               # bytes/s
 DEFAULT_STEPS = {W.C5.name: 8}
 
 
-# HBM traffic of the collision kernel from rocprofv3 counters, valid only for
-# the kernel sources it was measured on (see kernel_sources_digest).
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "collide_f32_gg_16x16x1_20cube_pmc.md")
+# HBM traffic of the collision kernel from rocprofv3 counters, one summary per
+# workload, valid only for the kernel sources it was measured on (see
+# kernel_sources_digest).
+def traffic_profile(workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"collide_f32_{workload}_hbm_counters.md")
+
+
 KERNEL_SOURCES = ("collide.hip", "collide.h", "qgbe_common.h", "api.hip")
 
 
@@ -86,7 +90,7 @@ def measured_traffic(workload: str):
     """HBM bytes per launch from the committed counter summary, or None when
     the summary is for another workload or for other kernel sources."""
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(traffic_profile(workload)).read()
     except OSError:
         return None
     fields = dict(line.split(":", 1) for line in text.splitlines() if line.startswith(("sources_sha256:", "workload:",
@@ -362,6 +366,9 @@ def run_workload(wl, N, steps, warmup, train_epochs, progress=False):
             slots -= SLOTS_DEPOSITS * accepted
     if sampler == qgbe.SAMPLER_LEARNED:
         slots += SLOTS_LEARNED_EXTRA * evals
+    # work over time of all collision launches of the timed steps: the average
+    # launch's work over its average duration
+    launches = sum(s["n_collide_launches"] for s in stats)
     achieved = slots / t_coll.sum()
     traffic = measured_traffic(wl.name) if N == wl.n_samples else None
     roof = dict(bound="alu", achieved=achieved, peak=ALU_PEAK_SLOTS, unit="lane-op slots/s",
@@ -369,8 +376,9 @@ def run_workload(wl, N, steps, warmup, train_epochs, progress=False):
                 traffic=traffic,
                 kernel="collide_roots_kernel" if roots else
                 ("collide_f32_kernel" if prec == qgbe.FP32 else "collide_f64_kernel"),
-                kernel_ms_avg=float(t_coll.mean() * 1e3),
-                hbm_frac=None if traffic is None else traffic / float(t_coll.mean()) / HBM_PEAK)
+                kernel_ms_avg=float(t_coll.sum() * 1e3 / launches),
+                launches_per_step=launches / len(stats),
+                hbm_frac=None if traffic is None else traffic * launches / float(t_coll.sum()) / HBM_PEAK)
     N0, E0 = stats[0]["N_total"], stats[0]["E_total"]
     rec = {
         "value": evals / elapsed, "steps": steps, "warmup": warmup, "ms_per_step": elapsed / steps * 1e3,

@@ -140,6 +140,9 @@ typedef struct {
    * isotropisation.                                                          */
   double entropy;
   double T_ii[3];
+  uint32_t n_collide_launches;  /* collision kernel launches of the term;
+                                   t_collide_ms is their sum            */
+  uint32_t reserved;
 } qgbe_stats;
 
 /* Optional outputs of the collision term (all may be NULL). */

@@ -171,6 +171,7 @@ qgbe_status run_collide(qgbe_ctx* c, int n_samples, int sampler, double* A, doub
   HIP_TRY(launch_zero_u64(c->d_count, kStripes, c->stream), "zero counter");
   HIP_TRY(launch_fill(c->d_mc, 0.0, 2 * kStripes, c->stream), "zero error accumulators");
   HIP_TRY(launch_fill(c->d_chan_var, 0.0, kStripes * std::max(1, c->nch), c->stream), "zero channel variances");
+  c->n_launches = 0;
   if (c->nch == 0) return QGBE_OK;
   CollideArgs a = base_args(c, n_samples, A, scale, items);
   a.learned = learned ? 1 : 0;
@@ -182,6 +183,7 @@ qgbe_status run_collide(qgbe_ctx* c, int n_samples, int sampler, double* A, doub
     a.group = c->d_all;
     a.n_group = c->nch;
     HIP_TRY(launch_collide_roots(a, sampler == QGBE_SAMPLER_ROOTS_ALT, c->stream), "collide (roots)");
+    ++c->n_launches;
     return QGBE_OK;
   }
   const bool f64_path = c->d.precision == QGBE_FP64;
@@ -189,6 +191,7 @@ qgbe_status run_collide(qgbe_ctx* c, int n_samples, int sampler, double* A, doub
     a.group = c->d_all;
     a.n_group = c->nch;
     HIP_TRY(launch_collide_f64(a, c->stream), "collide (fp64)");
+    ++c->n_launches;
     return QGBE_OK;
   }
   const int l = learned ? 1 : 0;
@@ -254,6 +257,7 @@ qgbe_status run_collide(qgbe_ctx* c, int n_samples, int sampler, double* A, doub
         }
         if (queue) a.lds_tiles = 0;  // the compacting variant reads f from the node quads
         HIP_TRY(launch_collide_f32(a, g.nslot, queue && n_pass == 1 && n_win == 1, c->stream), "collide (fp32)");
+        ++c->n_launches;
       }
     }
   }
@@ -594,6 +598,7 @@ qgbe_status qgbe_collision_term_ex(qgbe_ctx* c, int32_t n_samples, int32_t sampl
     float ms = 0.0f;
     (void)hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);
     st->t_collide_ms = ms;
+    st->n_collide_launches = (uint32_t)c->n_launches;
     st->n_evals = (double)c->G.cells * c->nch * c->G.nodes * n_samples;
   }
   return QGBE_OK;
@@ -672,6 +677,7 @@ qgbe_status qgbe_step(qgbe_ctx* c, double dt_fm, int32_t n_samples, int32_t samp
       float ms = 0.0f;
       (void)hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);
       per_step[k].t_collide_ms = ms;
+      per_step[k].n_collide_launches = (uint32_t)c->n_launches;
       (void)hipEventElapsedTime(&ms, c->ev[2], c->ev[3]);
       per_step[k].t_step_ms = ms;
       per_step[k].n_evals = (double)c->G.cells * c->nch * c->G.nodes * n_samples;

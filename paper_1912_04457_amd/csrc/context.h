@@ -64,6 +64,7 @@ struct qgbe_ctx {
   double* d_f_next = nullptr;
   float* d_f32 = nullptr;
   float4* d_f32q = nullptr;        // node quads of d_f32, for tiles read from global memory
+  int n_launches = 0;                    // collision kernel launches of the last term
   bool need_quads[2] = {false, false};  // some group reads tiles globally [uniform, learned]
   double* d_mass2 = nullptr;
   double* d_lag = nullptr;

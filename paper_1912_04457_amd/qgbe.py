@@ -62,7 +62,8 @@ class Stats(C.Structure):
                 ("t_collide_ms", C.c_double), ("t_step_ms", C.c_double), ("flags", C.c_uint32),
                 ("step", C.c_uint32), ("n_accepted", C.c_double), ("mc_err_est", C.c_double),
                 ("E_source", C.c_double), ("E_collide", C.c_double), ("E_total_mod", C.c_double),
-                ("entropy", C.c_double), ("T_ii", C.c_double * 3)]
+                ("entropy", C.c_double), ("T_ii", C.c_double * 3),
+                ("n_collide_launches", C.c_uint32), ("reserved", C.c_uint32)]
 
     def as_dict(self) -> dict:
         out = {}

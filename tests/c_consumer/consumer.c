@@ -23,6 +23,7 @@ int main(void) {
   FIELD(qgbe_stats, flags); FIELD(qgbe_stats, step); FIELD(qgbe_stats, n_accepted); FIELD(qgbe_stats, mc_err_est);
   FIELD(qgbe_stats, E_source); FIELD(qgbe_stats, E_collide); FIELD(qgbe_stats, E_total_mod);
   FIELD(qgbe_stats, entropy); FIELD(qgbe_stats, T_ii);
+  FIELD(qgbe_stats, n_collide_launches); FIELD(qgbe_stats, reserved);
   printf("sizeof qgbe_collide_extras %zu\n", sizeof(qgbe_collide_extras));
   FIELD(qgbe_collide_extras, scale); FIELD(qgbe_collide_extras, item_sums); FIELD(qgbe_collide_extras, on_device);
   printf("sizeof qgbe_train_cfg %zu\n", sizeof(qgbe_train_cfg));

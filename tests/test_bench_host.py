@@ -44,7 +44,7 @@ def test_traffic_reported_only_for_the_measured_sources():
     b = _bench()
     digest = b.kernel_sources_digest()
     assert len(digest) == 64
-    prof = open(os.path.join(ROOT, "profiles", "collide_f32_gg_16x16x1_20cube_pmc.md")).read()
+    prof = open(b.traffic_profile("gg_16x16x1_20cube_f32")).read()
     recorded = [l.split(":", 1)[1].strip() for l in prof.splitlines() if l.startswith("sources_sha256:")]
     assert len(recorded) == 1
     t = b.measured_traffic("gg_16x16x1_20cube_f32")

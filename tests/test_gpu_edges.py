@@ -83,7 +83,10 @@ def test_frozen_species_stay_fixed_across_steps(precision):
     with qgbe.Solver(n_x=n_x, n_p=n_p, x_half=(3.0, 3.0, 3.0), p_half=(2.0, 2.0, 2.0), species_mask=mask,
                      seed=SEED, precision=precision) as s:
         s.set_f(f)
-        s.step(0.01, 32, n_steps=3)
+        st = s.step(0.01, 32, n_steps=3)
+        # every step launches at least one collision kernel, the same launches each step
+        assert st[0]["n_collide_launches"] >= 1
+        assert all(x["n_collide_launches"] == st[0]["n_collide_launches"] for x in st)
         g1 = s.get_f()
         assert np.array_equal(g1[frozen], f[frozen])
         assert not np.array_equal(g1[0], f[0]) and not np.array_equal(g1[6], f[6])

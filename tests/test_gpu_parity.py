@@ -74,6 +74,7 @@ def test_gluon_config1(O, precision):
     scale_items = np.abs(r["I_ref"]).max()
     assert np.allclose(r["I"], r["I_ref"], rtol=TOL[precision], atol=TOL[precision] * scale_items)
     assert r["st"].n_evals == 1000 * 1000
+    assert r["st"].n_collide_launches >= 1
 
 
 @pytest.mark.parametrize("precision", [qgbe.FP64, qgbe.FP32])

@@ -170,9 +170,10 @@ __device__ __forceinline__ R matrix_element(int row, R s, R t, R u, R mu) {
 
 // |M|^2 / g^4 of a row: the user's terms where the row was replaced (the
 // row is uniform over a wavefront), else Table I.
-template <typename R>
+// kUser = false: no user terms in this launch (the table's rows only).
+template <typename R, bool kUser = true>
 __device__ __forceinline__ R msq_row(uint32_t mask, const MsqTable* tab, int row, R s, R t, R u, R mu) {
-  if (!((mask >> row) & 1u)) return matrix_element<R>(row, s, t, u, mu);
+  if (!kUser || !((mask >> row) & 1u)) return matrix_element<R>(row, s, t, u, mu);
   const R x[6] = {s, t, u, rcp_r<R>(t - mu), rcp_r<R>(u - mu), rcp_r<R>(s)};
   R sum = R(0);
   const int n = tab->n[row];
@@ -630,9 +631,9 @@ __device__ __forceinline__ R prefactor(const Item& it, const Geo& g) {
   return (R)it.pref * (R)g.pstar * (R)g.rs * rcp_r<R>((R)g.E2);
 }
 
-template <typename R>
+template <typename R, bool kUser = true>
 __device__ __forceinline__ R weight_no_bracket(const CollideArgs& A, const Item& it, const Geo& g, int row) {
-  const R m = msq_row<R>(A.msq_mask, A.msq, row, (R)g.s, (R)g.t, (R)g.u, (R)it.mu);
+  const R m = msq_row<R, kUser>(A.msq_mask, A.msq, row, (R)g.s, (R)g.t, (R)g.u, (R)it.mu);
   return m * prefactor<R>(it, g);
 }
 
@@ -1157,7 +1158,10 @@ constexpr int f32_block(bool queue) { return queue ? kQueueWaves * 64 : kF32Thre
 // of the next 64 samples runs, a third before, between and after it, so the
 // LDS works off the atomics behind VALU work.  Same arithmetic per sample as
 // the direct loop.
-template <bool kSym, bool kScale, bool kAllLds, bool kLearned, bool kQueue>
+// kUser: some row of the matrix-element table is replaced by user terms; the
+// variants without them carry no code for the user-term evaluation (which
+// otherwise holds registers across the sample loop: 6% of the 7-species term).
+template <bool kSym, bool kScale, bool kAllLds, bool kLearned, bool kQueue, bool kUser>
 __global__ __launch_bounds__(f32_block(kQueue)) void collide_f32_kernel(CollideArgs A) {
   static_assert(!kQueue || (kSym && kAllLds && !kLearned), "the queue serves the uniform sampler, slots in LDS");
   // kAllLds: every f tile and accumulator in LDS (the queue variant: every
@@ -1272,7 +1276,7 @@ __global__ __launch_bounds__(f32_block(kQueue)) void collide_f32_kernel(CollideA
     auto evaluate = [&](const double u[5], float inv_q) {
       Geo g;
       if (!geometry(it, G, u, g)) return;
-      finish(g, weight_no_bracket<float>(A, it, g, ch.row) * inv_q);
+      finish(g, weight_no_bracket<float, kUser>(A, it, g, ch.row) * inv_q);
     };
     if (kQueue) {
       // queued record -> the accepted sample's geometry, as geometry() left it
@@ -1285,7 +1289,7 @@ __global__ __launch_bounds__(f32_block(kQueue)) void collide_f32_kernel(CollideA
           g.p3[a] = q_p3[wid][a][slot];
           g.p4[a] = (it.p1[a] + g.p2[a]) - g.p3[a];
         }
-        const float m = msq_row<float>(A.msq_mask, A.msq, ch.row, q_f[wid][0][slot], q_f[wid][1][slot],
+        const float m = msq_row<float, kUser>(A.msq_mask, A.msq, ch.row, q_f[wid][0][slot], q_f[wid][1][slot],
                                        q_f[wid][2][slot], (float)it.mu);
         finish(g, m * q_f[wid][3][slot]);
       };
@@ -1514,19 +1518,25 @@ hipError_t launch_collide_f64(const CollideArgs& a, hipStream_t stream) {
   return hipGetLastError();
 }
 
+template <bool kSym, bool kScale, bool kAllLds, bool kLearned, bool kQueue>
+void launch_f32_user(const CollideArgs& a, dim3 grid, dim3 block, size_t lds, hipStream_t st) {
+  if (a.msq_mask)
+    hipLaunchKernelGGL((collide_f32_kernel<kSym, kScale, kAllLds, kLearned, kQueue, true>), grid, block, lds, st, a);
+  else
+    hipLaunchKernelGGL((collide_f32_kernel<kSym, kScale, kAllLds, kLearned, kQueue, false>), grid, block, lds, st, a);
+}
+
 template <bool kSym, bool kScale, bool kLearned>
 void launch_f32_variant(const CollideArgs& a, bool all_lds, bool queue, dim3 grid, dim3 block, size_t lds,
                         hipStream_t st) {
   if constexpr (kSym && !kLearned) {
     if (queue) {
-      hipLaunchKernelGGL((collide_f32_kernel<true, kScale, true, false, true>), grid, block, lds, st, a);
+      launch_f32_user<true, kScale, true, false, true>(a, grid, block, lds, st);
       return;
     }
   }
-  if (all_lds)
-    hipLaunchKernelGGL((collide_f32_kernel<kSym, kScale, true, kLearned, false>), grid, block, lds, st, a);
-  else
-    hipLaunchKernelGGL((collide_f32_kernel<kSym, kScale, false, kLearned, false>), grid, block, lds, st, a);
+  if (all_lds) launch_f32_user<kSym, kScale, true, kLearned, false>(a, grid, block, lds, st);
+  else launch_f32_user<kSym, kScale, false, kLearned, false>(a, grid, block, lds, st);
 }
 
 template <bool kSym, bool kScale>
@@ -1567,25 +1577,19 @@ hipError_t set_collide_lds_limit(size_t lds_max, size_t* budget_plain, size_t* b
   // runtime's default; after a refusal the budget is the limit in force.
   // Groups: 0 uniform sampler, 1 learned sampler, 2 the compacting variant.
   struct Fn { const void* fn; int group; };
-  const Fn fns[18] = {
-      {(const void*)collide_f32_kernel<true, true, true, false, false>, 0},
-      {(const void*)collide_f32_kernel<true, false, true, false, false>, 0},
-      {(const void*)collide_f32_kernel<false, true, true, false, false>, 0},
-      {(const void*)collide_f32_kernel<false, false, true, false, false>, 0},
-      {(const void*)collide_f32_kernel<true, true, false, false, false>, 0},
-      {(const void*)collide_f32_kernel<true, false, false, false, false>, 0},
-      {(const void*)collide_f32_kernel<false, true, false, false, false>, 0},
-      {(const void*)collide_f32_kernel<false, false, false, false, false>, 0},
-      {(const void*)collide_f32_kernel<true, true, true, true, false>, 1},
-      {(const void*)collide_f32_kernel<true, false, true, true, false>, 1},
-      {(const void*)collide_f32_kernel<false, true, true, true, false>, 1},
-      {(const void*)collide_f32_kernel<false, false, true, true, false>, 1},
-      {(const void*)collide_f32_kernel<true, true, false, true, false>, 1},
-      {(const void*)collide_f32_kernel<true, false, false, true, false>, 1},
-      {(const void*)collide_f32_kernel<false, true, false, true, false>, 1},
-      {(const void*)collide_f32_kernel<false, false, false, true, false>, 1},
-      {(const void*)collide_f32_kernel<true, true, true, false, true>, 2},
-      {(const void*)collide_f32_kernel<true, false, true, false, true>, 2}};
+#define QGBE_F32_PAIR(S, Sc, L, Le, Q, G) \
+  {(const void*)collide_f32_kernel<S, Sc, L, Le, Q, false>, G}, {(const void*)collide_f32_kernel<S, Sc, L, Le, Q, true>, G}
+  const Fn fns[36] = {
+      QGBE_F32_PAIR(true, true, true, false, false, 0),   QGBE_F32_PAIR(true, false, true, false, false, 0),
+      QGBE_F32_PAIR(false, true, true, false, false, 0),  QGBE_F32_PAIR(false, false, true, false, false, 0),
+      QGBE_F32_PAIR(true, true, false, false, false, 0),  QGBE_F32_PAIR(true, false, false, false, false, 0),
+      QGBE_F32_PAIR(false, true, false, false, false, 0), QGBE_F32_PAIR(false, false, false, false, false, 0),
+      QGBE_F32_PAIR(true, true, true, true, false, 1),    QGBE_F32_PAIR(true, false, true, true, false, 1),
+      QGBE_F32_PAIR(false, true, true, true, false, 1),   QGBE_F32_PAIR(false, false, true, true, false, 1),
+      QGBE_F32_PAIR(true, true, false, true, false, 1),   QGBE_F32_PAIR(true, false, false, true, false, 1),
+      QGBE_F32_PAIR(false, true, false, true, false, 1),  QGBE_F32_PAIR(false, false, false, true, false, 1),
+      QGBE_F32_PAIR(true, true, true, false, true, 2),    QGBE_F32_PAIR(true, false, true, false, true, 2)};
+#undef QGBE_F32_PAIR
   size_t budget[3] = {lds_max, lds_max, lds_max};
   for (const Fn& f : fns) {
     hipFuncAttributes attr;

@@ -115,6 +115,11 @@ def parse():
                     help="run one device copy of this many MiB before timing (counter calibration)")
     ap.add_argument("--no-sub", action="store_true", help="skip the pure-gluon spatial sub-record")
     ap.add_argument("--progress", action="store_true", help="print a line per timed step on stderr")
+    ap.add_argument("--save-proposal", default="", help="learned sampler: save the trained table (.npz)")
+    ap.add_argument("--load-proposal", default="",
+                    help="learned sampler: install a table saved by --save-proposal instead of training")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="learned sampler: skip the learned and plain terms after the timed steps")
     ap.add_argument("--no-fixed-error", action="store_true",
                     help="skip the plain-vs-learned time per step at fixed MC error")
     ap.add_argument("--replicas", type=int, default=8)
@@ -153,6 +158,25 @@ def train_proposal(solver, wl, epochs, target_rows=1_000_000):
     flags, _ = qgbe.qgbe_proposal_judge(solver.ctx, 32, 1, solver.n_channels)
     return dict(train_rows=n_rows, train_epochs=epochs, train_s=train_s, train_loss_last=float(losses[-1]),
                 learned_channels=int(flags.sum()), channels=solver.n_channels)
+
+
+def save_proposal(solver, wl, path):
+    """The proposal table and per-channel sampler flags as an .npz file."""
+    rows = solver.n_channels * wl.nodes
+    thr, mu, sg = qgbe.qgbe_get_proposal_table(solver.ctx, rows)
+    samplers = qgbe.qgbe_get_channel_samplers(solver.ctx, solver.n_channels)
+    np.savez(path, thr=thr, mu=mu, sigma=sg, samplers=samplers)
+
+
+def load_proposal(solver, wl, path):
+    """Install a table saved by save_proposal (no recording, training or judge)."""
+    z = np.load(path)
+    rows = solver.n_channels * wl.nodes
+    if z["thr"].shape[0] != rows or z["samplers"].shape != (solver.n_channels,):
+        raise ValueError(f"{path}: table for another grid ({z['thr'].shape[0]} rows, {rows} expected)")
+    qgbe.qgbe_set_proposal_table(solver.ctx, z["thr"], z["mu"], z["sigma"])
+    qgbe.qgbe_set_channel_samplers(solver.ctx, z["samplers"])
+    return dict(loaded=os.path.basename(path), learned_channels=int(z["samplers"].sum()), channels=solver.n_channels)
 
 
 def fixed_error(R, epochs):
@@ -304,11 +328,12 @@ def cpu_baseline(wl, f, n_samples, budget_s, table=None):
                        f"{total_t:.1f} s, FP64, OpenMP)")
 
 
-def run_workload(wl, N, steps, warmup, train_epochs, progress=False):
+def run_workload(wl, N, steps, warmup, train_epochs, progress=False, proposal_in=None, proposal_out=None,
+                 compare=True):
     """Time `steps` steps of a workload after `warmup` untimed ones; the learned
-    sampler is trained first (outside the timed region).  Returns the fields of
-    a bench record and the solver's proposal table (learned runs) for the CPU
-    baseline."""
+    sampler is trained first (outside the timed region), or its table loaded
+    from proposal_in.  Returns the fields of a bench record and the solver's
+    proposal table (learned runs) for the CPU baseline."""
     import torch
     f0 = W.initial_f(wl)
     prec = qgbe.FP64 if wl.precision == "f64" else qgbe.FP32
@@ -322,7 +347,9 @@ def run_workload(wl, N, steps, warmup, train_epochs, progress=False):
     roots = sampler in (qgbe.SAMPLER_ROOTS, qgbe.SAMPLER_ROOTS_ALT)
     prep, table = None, None
     if sampler == qgbe.SAMPLER_LEARNED:
-        prep = train_proposal(solver, wl, train_epochs)
+        prep = load_proposal(solver, wl, proposal_in) if proposal_in else train_proposal(solver, wl, train_epochs)
+        if proposal_out:
+            save_proposal(solver, wl, proposal_out)
     if warmup:
         solver.step(wl.dt_fm, N, n_steps=warmup, sampler=sampler)
     if sampler == qgbe.SAMPLER_LEARNED:   # the table the timed steps start from (CPU baseline input)
@@ -341,8 +368,8 @@ def run_workload(wl, N, steps, warmup, train_epochs, progress=False):
         stats = solver.step(wl.dt_fm, N, n_steps=steps, sampler=sampler)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    compare = None
-    if sampler == qgbe.SAMPLER_LEARNED:
+    want_compare, compare = compare, None
+    if sampler == qgbe.SAMPLER_LEARNED and want_compare:
         # after the timed steps, on the same f: one learned and one plain collision
         # term with the same samples per point (the learned one from the proposal
         # table shared by all cells): estimated MC error and kernel time of each
@@ -421,7 +448,9 @@ def main():
     wl = W.WORKLOADS[a.workload]
     N = a.samples or wl.n_samples
     steps = a.steps or DEFAULT_STEPS.get(wl.name, wl.steps)
-    rec, f0, table = run_workload(wl, N, steps, a.warmup, a.train_epochs, a.progress)
+    rec, f0, table = run_workload(wl, N, steps, a.warmup, a.train_epochs, a.progress,
+                                  proposal_in=a.load_proposal or None, proposal_out=a.save_proposal or None,
+                                  compare=not a.no_compare)
     out = {"metric": METRIC, "value": rec.pop("value"), "unit": "evals/s", "n_gpus": 1,
            "steps": rec.pop("steps"), "warmup": rec.pop("warmup"), "ms_per_step": rec.pop("ms_per_step"),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": rec.pop("dtype"),

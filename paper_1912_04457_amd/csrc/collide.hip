@@ -1181,8 +1181,27 @@ __global__ __launch_bounds__(f32_block(kQueue)) void collide_f32_kernel(CollideA
   const int nw = blockDim.x / kWave;
   const int lb = xcd_local_block(blockIdx.x, gridDim.x);
   const int chunk = lb % A.n_chunks;
-  const int gi = (lb / A.n_chunks) % A.n_group;
-  const int cell = lb / (A.n_chunks * A.n_group);
+  // Uniform sampler: the chunks and channels of one cell follow each other
+  // (they share its f quads and output rows in the XCD's L2).  Learned
+  // sampler: blocks of 32 cells (the workgroups one XCD holds at a time),
+  // and within a block the cells of one channel follow each other, so the
+  // channel's proposal rows, shared by all cells, are read from HBM about
+  // once per block instead of once per cell, and the block's f rows serve
+  // every channel.
+  int gi, cell;
+  if (kLearned) {
+    constexpr int kCellBlock = 32;
+    const int u = lb / A.n_chunks;
+    const int per = A.n_group * kCellBlock;
+    const int cb = u / per;
+    const int S = min(kCellBlock, G.cells - cb * kCellBlock);  // the last block may be short
+    const int r = u - cb * per;
+    gi = r / S;
+    cell = cb * kCellBlock + r % S;
+  } else {
+    gi = (lb / A.n_chunks) % A.n_group;
+    cell = lb / (A.n_chunks * A.n_group);
+  }
   const int ci = A.group[gi];
   const Channel ch = A.chans[ci];
   const int nslot = ch.nslot;

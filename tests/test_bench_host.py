@@ -1,10 +1,13 @@
 """Host-side checks of bench.py (no GPU): the one-GPU refusal, how the slot
-counts the roofline uses are composed, and that the committed HBM-traffic
-figure is only reported for the kernel sources it was measured on."""
+counts the roofline uses are composed, that the committed HBM-traffic figure
+is only reported for the kernel sources it was measured on, and that a saved
+proposal table for another grid is refused."""
 import importlib.util
 import os
 import subprocess
 import sys
+
+import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -53,3 +56,30 @@ def test_traffic_reported_only_for_the_measured_sources():
     else:                          # sources changed since: no stale figure
         assert t is None
     assert b.measured_traffic("no_such_workload") is None
+
+
+def test_load_proposal_refuses_a_table_for_another_grid(tmp_path):
+    """--load-proposal checks the table's rows (channels x nodes) and the
+    per-channel flags against the grid before anything reaches the device."""
+    import numpy as np
+
+    b = _bench()
+
+    class _Solver:
+        n_channels = 70
+        ctx = None
+
+    class _Wl:
+        nodes = 16 ** 3
+
+    path = str(tmp_path / "p.npz")
+    rows = 70 * 20 ** 3                                   # a 20^3 table
+    np.savez(path, thr=np.zeros((rows, 8), np.uint32), mu=np.zeros((rows, 8, 5), np.float32),
+             sigma=np.ones((rows, 8, 5), np.float32), samplers=np.ones(70, np.uint8))
+    with pytest.raises(ValueError, match="another grid"):
+        b.load_proposal(_Solver(), _Wl(), path)
+    rows = 70 * 16 ** 3                                   # right rows, flags for 7 channels
+    np.savez(path, thr=np.zeros((rows, 8), np.uint32), mu=np.zeros((rows, 8, 5), np.float32),
+             sigma=np.ones((rows, 8, 5), np.float32), samplers=np.ones(7, np.uint8))
+    with pytest.raises(ValueError, match="another grid"):
+        b.load_proposal(_Solver(), _Wl(), path)

@@ -52,6 +52,31 @@ def test_user_rows_match_oracle(O_user, precision, tol):
         assert abs(A[:, cell].sum()) <= 1e-13 * S[:, cell].sum()
 
 
+def test_user_rows_fp32_step_variants(O_user):
+    """The variants a step launches (no scale output), uniform and learned
+    sampler, with user rows: FP32 within 1e-4 of the cell scale."""
+    _case("user msq fp32 without scale, uniform and learned")
+    O = O_user
+    g = O.Grid(n_x=(2, 1, 1), n_p=(6, 5, 7), p_half=(2.0, 2.0, 2.0), species_mask=0x7F)
+    f = W.random_f(54, g.cells, g.nodes) * 0.6
+    rows = len(O.channels(g)) * g.nodes
+    thr, mu, sg = W.random_mog_table(55, rows, K=8, alpha=0.1, mu_scale=1.0, log_sigma=(-1.0, 0.5))
+    with _solver(g, qgbe.FP32) as s:
+        for row, terms in USER.items():
+            qgbe.qgbe_set_matrix_element(s.ctx, row, terms)
+        s.set_f(f)
+        qgbe.qgbe_set_step_index(s.ctx, 0)
+        A_u = s.collision(40)[0]
+        qgbe.qgbe_set_proposal_table(s.ctx, thr, mu, sg)
+        qgbe.qgbe_set_step_index(s.ctx, 2)
+        A_l = s.collision(40, sampler=qgbe.SAMPLER_LEARNED)[0]
+        m = s.masses()
+    A_ref, S_ref, _ = O.collision(g, f, m, SEED, 0, 40)
+    assert np.all(np.abs(A_u - A_ref) <= 1e-4 * S_ref + 1e-300)
+    A_lref, S_lref, _ = O.collision_learned(g, f, m, SEED, 2, 40, thr, mu, sg)
+    assert np.all(np.abs(A_l - A_lref) <= 1e-4 * S_lref + 1e-300)
+
+
 def test_user_rows_in_the_root_sampler(O_user):
     _case("user msq roots")
     O = O_user

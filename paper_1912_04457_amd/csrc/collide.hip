@@ -55,31 +55,30 @@ __device__ __forceinline__ double sqrt64(double x) { return x > 0.0 ? x * rsqrt6
 
 // sin and cos of 2 pi u for u in [0, 1).  With x = 2u = q/2 + r, q the
 // nearest multiple of 1/2 (exact: u has at most 24 significant bits) and
-// |r| <= 1/4, the Taylor series of sin(pi r) to r^15 and of cos(pi r) to
-// r^16 are accurate to 3e-17 and 2e-18, and the quadrant q mod 4 permutes
-// and negates them.
+// |r| <= 1/4, sin(pi r) = r S(r^2) and cos(pi r) = C(r^2) with S and C of
+// degree 6 (Chebyshev-node fits, gen_fp64_poly.py; fit errors 1e-17 and
+// 5e-17), and the quadrant q mod 4 permutes and negates them.  Measured on
+// the CPU over every 23-bit u: within 1.8e-16 of sin and cos (the Taylor
+// series to r^15 and r^16 it replaces: 1.9e-16).
 __device__ __forceinline__ void sincos_2pi(double u, double& sn, double& cs) {
   const double x = 2.0 * u;
   const double q = rint(2.0 * x);
   const double r = fma(-0.5, q, x);
   const double r2 = r * r;
-  double ps = -2.1915353447830217e-05;
-  ps = fma(ps, r2, 0.00046630280576761255);
-  ps = fma(ps, r2, -0.0073704309457143504);
-  ps = fma(ps, r2, 0.08214588661112823);
-  ps = fma(ps, r2, -0.5992645293207921);
-  ps = fma(ps, r2, 2.5501640398773455);
-  ps = fma(ps, r2, -5.16771278004997);
+  double ps = 0.0004615313805851339;
+  ps = fma(ps, r2, -0.0073700215052934955);
+  ps = fma(ps, r2, 0.08214586917478434);
+  ps = fma(ps, r2, -0.5992645289394928);
+  ps = fma(ps, r2, 2.550164039873374);
+  ps = fma(ps, r2, -5.167712780049954);
   ps = fma(ps, r2, 3.141592653589793);
   ps *= r;
-  double pc = 4.303069587032947e-06;
-  pc = fma(pc, r2, -0.0001046381049248457);
-  pc = fma(pc, r2, 0.0019295743094039231);
-  pc = fma(pc, r2, -0.02580689139001406);
-  pc = fma(pc, r2, 0.2353306303588932);
-  pc = fma(pc, r2, -1.3352627688545895);
-  pc = fma(pc, r2, 4.0587121264167685);
-  pc = fma(pc, r2, -4.934802200544679);
+  double pc = 0.001906807054314109;
+  pc = fma(pc, r2, -0.025804938121446575);
+  pc = fma(pc, r2, 0.23533054718578558);
+  pc = fma(pc, r2, -1.3352627670358546);
+  pc = fma(pc, r2, 4.058712126397826);
+  pc = fma(pc, r2, -4.934802200544605);
   pc = fma(pc, r2, 1.0);
   const int k = (int)q;
   const double a = (k & 1) ? pc : ps;   // sin before the sign
@@ -89,32 +88,34 @@ __device__ __forceinline__ void sincos_2pi(double u, double& sn, double& cs) {
 }
 
 // e^x: x = k ln2 + r with |r| <= ln2/2 (ln2 split so k*ln2_hi is exact for
-// |k| < 2^11), the Taylor series of e^r to r^13 (remainder < 5e-18), times
-// 2^k.  Overflows to inf and underflows to 0 like exp.
+// |k| < 2^11), e^r = 1 + r (1 + r g(r)) with g of degree 9 (a Chebyshev-node
+// fit, gen_fp64_poly.py; relative error of e^r from the fit 2e-17), times
+// 2^k.  Overflows to inf and underflows to 0 like exp.  Measured on the CPU:
+// within 0.95 ulp over |x| < 700 (the Taylor series to r^13 it replaces: 0.89).
 __device__ __forceinline__ double exp64(double x) {
   const double k = rint(x * 1.4426950408889634);
   double r = fma(-k, 0.6931471805598903, x);
   r = fma(-k, 5.497923018708371e-14, r);
-  double p = 1.6059043836821613e-10;
-  p = fma(p, r, 2.08767569878681e-09);
-  p = fma(p, r, 2.505210838544172e-08);
-  p = fma(p, r, 2.755731922398589e-07);
-  p = fma(p, r, 2.7557319223985893e-06);
-  p = fma(p, r, 2.48015873015873e-05);
-  p = fma(p, r, 0.0001984126984126984);
-  p = fma(p, r, 0.001388888888888889);
-  p = fma(p, r, 0.008333333333333333);
-  p = fma(p, r, 0.041666666666666664);
-  p = fma(p, r, 0.16666666666666666);
-  p = fma(p, r, 0.5);
+  double p = 2.510038549551032e-08;
+  p = fma(p, r, 2.7620088445409746e-07);
+  p = fma(p, r, 2.7557268459997064e-06);
+  p = fma(p, r, 2.4801521295954376e-05);
+  p = fma(p, r, 0.00019841269863053618);
+  p = fma(p, r, 0.0013888888917213717);
+  p = fma(p, r, 0.008333333333330062);
+  p = fma(p, r, 0.04166666666662413);
+  p = fma(p, r, 0.16666666666666669);
+  p = fma(p, r, 0.5000000000000001);
   p = fma(p, r, 1.0);
   p = fma(p, r, 1.0);
   return ldexp(p, (int)k);
 }
 
 // ln a for finite a > 0: a = m 2^e with m in [1/sqrt2, sqrt2), ln m =
-// 2 atanh(s), s = (m-1)/(m+1), |s| <= 0.172, by its series to s^21
-// (remainder < 1e-17).
+// 2 atanh(s) = 2 s P(s^2), s = (m-1)/(m+1), |s| <= 0.172, P of degree 7 (a
+// Chebyshev-node fit of atanh(sqrt w)/sqrt w, gen_fp64_poly.py; relative
+// fit error 1e-18).  Measured on the CPU: within 2.1 ulp of ln on the 23-bit
+// uniforms, 2.7 ulp elsewhere (the series to s^21 it replaces: the same).
 __device__ __forceinline__ double log64(double a) {
   int e;
   double m = frexp(a, &e);
@@ -124,16 +125,13 @@ __device__ __forceinline__ double log64(double a) {
   }
   const double s = (m - 1.0) * rcp64(m + 1.0);
   const double s2 = s * s;
-  double p = 0.047619047619047616;
-  p = fma(p, s2, 0.05263157894736842);
-  p = fma(p, s2, 0.058823529411764705);
-  p = fma(p, s2, 0.06666666666666667);
-  p = fma(p, s2, 0.07692307692307693);
-  p = fma(p, s2, 0.09090909090909091);
-  p = fma(p, s2, 0.1111111111111111);
-  p = fma(p, s2, 0.14285714285714285);
-  p = fma(p, s2, 0.2);
-  p = fma(p, s2, 0.3333333333333333);
+  double p = 0.07404933786156531;
+  p = fma(p, s2, 0.0765625655736915);
+  p = fma(p, s2, 0.09091816120808513);
+  p = fma(p, s2, 0.11111098523202137);
+  p = fma(p, s2, 0.1428571438036914);
+  p = fma(p, s2, 0.19999999999650955);
+  p = fma(p, s2, 0.33333333333333826);
   p = fma(p, s2, 1.0);
   const double de = (double)e;
   return fma(de, 0.6931471805598903, fma(de, 5.497923018708371e-14, 2.0 * s * p));

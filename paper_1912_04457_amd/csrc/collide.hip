@@ -535,7 +535,7 @@ __device__ __forceinline__ void mix_prepare_f32(const uint32_t* thr, const float
                                                 float* row, int lane) {
   for (int i = lane; i < K * 5; i += kWave) {
     row[i] = mu[i];
-    row[40 + i] = (float)rcp64((double)sg[i]);
+    row[40 + i] = (float)(rcp64((double)sg[i]) * 0.70710678118654752);
     row[kMixSigma + i] = sg[i];
   }
   // log pi_k - sum_d log sigma_kd - 5/2 log 2pi: the K x 6 logarithms one per
@@ -579,18 +579,22 @@ __device__ __forceinline__ float mix_density_f32(const float* row, int K, const 
 #pragma unroll
       for (int d = 0; d < 5; ++d) {
         const float z = (yf[d] - row[k * 5 + d]) * row[40 + k * 5 + d];
-        l = fmaf(-0.5f * z, z, l);
+        l = fmaf(-z, z, l);
       }
       acc += exp_f32(l);
     }
   }
   float lq = log_f32(acc);
-  // log(u (1 - u)) = -|y| - 2 log(1 + e^-|y|)
+  // log(u (1 - u)) = -|y| - 2 log(1 + e^-|y|); the five factors 1 + e^-|y|
+  // lie in [1, 2], so their product takes one logarithm
+  float prod = 1.0f;
 #pragma unroll
   for (int d = 0; d < 5; ++d) {
     const float a = fabsf(yf[d]);
-    lq += a + 2.0f * log_f32(1.0f + exp_f32(-a));
+    lq += a;
+    prod *= 1.0f + exp_f32(-a);
   }
+  lq += 2.0f * log_f32(prod);
   return row[88] + exp_f32(lq);
 }
 

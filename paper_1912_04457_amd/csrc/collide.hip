@@ -273,7 +273,7 @@ struct Item {
   int cell, p1_lin;
   double p1[3];
   double E1;
-  double m2sq, m3sq, m4sq;
+  double m1sq, m2sq, m3sq, m4sq;
   double dm34;              // m3^2 - m4^2
   double sum2, dif2;        // (m3 + m4)^2 (the threshold of s), (m3 - m4)^2
   double mu;                // regulator m_g^2
@@ -599,9 +599,27 @@ __device__ __forceinline__ float mix_density_f32(const float* row, int K, const 
 }
 
 // Set up the wave-uniform item constants.
-__device__ __forceinline__ void load_item(Item& it, const CollideArgs& A, const Channel& ch, int cell, int p1_lin) {
+// The item constants of a (cell, channel) pair: masses, threshold terms and
+// the channel coefficient (the same for every observed node of the pair).
+__device__ __forceinline__ void item_pair(Item& it, const CollideArgs& A, const Channel& ch, int cell) {
   const Grid& G = A.G;
   it.cell = cell;
+  it.m1sq = A.mass2[ch.sp[0] * G.cells + cell];
+  it.m2sq = A.mass2[ch.sp[1] * G.cells + cell];
+  it.m3sq = A.mass2[ch.sp[2] * G.cells + cell];
+  it.m4sq = A.mass2[ch.sp[3] * G.cells + cell];
+  it.mu = A.mass2[kGluon * G.cells + cell];
+  const double m3 = sqrt(it.m3sq), m4 = sqrt(it.m4sq);
+  it.sum2 = (m3 + m4) * (m3 + m4);
+  it.dif2 = (m3 - m4) * (m3 - m4);
+  it.dm34 = it.m3sq - it.m4sq;
+  const double V5 = G.Vp * 4.0 * kPi;
+  it.coef = (A.symmetric ? ch.w : ch.sigma) * V5 / (double)A.n_samples;
+}
+
+// The observed node's part of the item constants (p1, E1, f1, prefactor).
+__device__ __forceinline__ void item_node(Item& it, const CollideArgs& A, const Channel& ch, int p1_lin) {
+  const Grid& G = A.G;
   it.p1_lin = p1_lin;
   const int iz = p1_lin % G.np[2];
   const int iy = (p1_lin / G.np[2]) % G.np[1];
@@ -609,20 +627,14 @@ __device__ __forceinline__ void load_item(Item& it, const CollideArgs& A, const 
   it.p1[0] = -G.ph[0] + (ix + 0.5) * G.dp[0];
   it.p1[1] = -G.ph[1] + (iy + 0.5) * G.dp[1];
   it.p1[2] = -G.ph[2] + (iz + 0.5) * G.dp[2];
-  const double m1sq = A.mass2[ch.sp[0] * G.cells + cell];
-  it.m2sq = A.mass2[ch.sp[1] * G.cells + cell];
-  it.m3sq = A.mass2[ch.sp[2] * G.cells + cell];
-  it.m4sq = A.mass2[ch.sp[3] * G.cells + cell];
-  it.mu = A.mass2[kGluon * G.cells + cell];
-  it.E1 = sqrt(it.p1[0] * it.p1[0] + it.p1[1] * it.p1[1] + it.p1[2] * it.p1[2] + m1sq);
-  const double m3 = sqrt(it.m3sq), m4 = sqrt(it.m4sq);
-  it.sum2 = (m3 + m4) * (m3 + m4);
-  it.dif2 = (m3 - m4) * (m3 - m4);
-  it.dm34 = it.m3sq - it.m4sq;
-  it.f1 = A.f64[((size_t)ch.sp[0] * G.cells + cell) * G.nodes + p1_lin];
-  const double V5 = G.Vp * 4.0 * kPi;
-  it.coef = (A.symmetric ? ch.w : ch.sigma) * V5 / (double)A.n_samples;
+  it.E1 = sqrt(it.p1[0] * it.p1[0] + it.p1[1] * it.p1[1] + it.p1[2] * it.p1[2] + it.m1sq);
+  it.f1 = A.f64[((size_t)ch.sp[0] * G.cells + it.cell) * G.nodes + p1_lin];
   it.pref = it.coef * G.g4 * kNorm / it.E1;
+}
+
+__device__ __forceinline__ void load_item(Item& it, const CollideArgs& A, const Channel& ch, int cell, int p1_lin) {
+  item_pair(it, A, ch, cell);
+  item_node(it, A, ch, p1_lin);
 }
 
 
@@ -1231,9 +1243,20 @@ __global__ __launch_bounds__(f32_block(kQueue)) void collide_f32_kernel(CollideA
   const bool g3 = is_gluon(ch.sp[2]), g4 = is_gluon(ch.sp[3]);
   const int first = chunk * A.chunk_items;
   const int last = min(first + A.chunk_items, nodes);
+  // Learned sampler (short items): the (cell, channel) constants once per
+  // workgroup.  The uniform sampler's long items recompute them per item:
+  // held across its item loop they cost more spilled registers in the
+  // sample loop than they save.
+  Item pair;
+  if (kLearned) item_pair(pair, A, ch, cell);
   for (int p1_lin = first + wid; p1_lin < last; p1_lin += nw) {
     Item it;
-    load_item(it, A, ch, cell, p1_lin);
+    if (kLearned) {
+      it = pair;
+      item_node(it, A, ch, p1_lin);
+    } else {
+      load_item(it, A, ch, cell, p1_lin);
+    }
     if (!(it.E1 > 0.0)) {  // massless p = 0 node: zero measure
       if (lane == 0 && A.items && A.direct) A.items[((size_t)cell * A.n_channels + ci) * nodes + p1_lin] = 0.0;
       continue;
@@ -1381,7 +1404,7 @@ __global__ __launch_bounds__(f32_block(kQueue)) void collide_f32_kernel(CollideA
         const uint32_t xw[8] = {x0, x1, x2, x3, y0, y1, y2, y3};
         float yl[5];
         mix_draw_row(xw, A.mix_thr + mrow * A.mix_K, mix_rows[wid], A.mix_K, u, yl);
-        inv_q = 1.0f / mix_density_f32(mix_rows[wid], A.mix_K, yl);
+        inv_q = __builtin_amdgcn_rcpf(mix_density_f32(mix_rows[wid], A.mix_K, yl));  // about 1 ulp; q >= alpha
       } else {
         five_uniforms(x0, x1, x2, x3, u);
       }

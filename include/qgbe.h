@@ -296,7 +296,9 @@ qgbe_status qgbe_observables(qgbe_ctx* ctx, qgbe_stats* st);
  * array, so calls that overlap on one GPU (other streams, other threads)
  * race; calls in sequence on one stream do not.  Asynchronous on desc->stream
  * except that the first call, and any call whose channel table differs from
- * the previous call's, waits for its upload of the table.  No statistics. */
+ * the previous call's, waits for its upload of the table (a caller that
+ * captures the stream makes one call with the same grid before capturing).
+ * No statistics. */
 qgbe_status qgbe_collision_term_noalloc(const qgbe_grid_desc* desc, const double* f, uint32_t step,
                                         int32_t n_samples, int32_t sampler, double* A);
 

@@ -132,8 +132,9 @@ qgbe_status qgbe_collision_term_noalloc(const qgbe_grid_desc* desc, const double
   c.d_f = const_cast<double*>(f);  // read only: masses and the collision kernels
 
   // Channel table, group lists and identity list, uploaded when they differ
-  // from what this device's scratch holds (then waited for, so the host copy
-  // can be reused by the next call).
+  // from what this device's scratch holds and waited for; the host record of
+  // what the scratch holds changes only after the upload has completed, so a
+  // failed upload is retried by the next call.
   std::vector<unsigned char> tab(table_bytes, 0);
   std::memcpy(tab.data(), c.chans.data(), c.chans.size() * sizeof(Channel));
   std::memcpy(tab.data() + ((unsigned char*)c.d_groups - dev->ptr), c.group_index.data(),
@@ -143,10 +144,11 @@ qgbe_status qgbe_collision_term_noalloc(const qgbe_grid_desc* desc, const double
   {
     std::lock_guard<std::mutex> lock(g_mu);
     if (dev->table != tab) {
-      dev->table = tab;
-      HIP_TRY(hipMemcpyAsync(dev->ptr, dev->table.data(), table_bytes, hipMemcpyHostToDevice, c.stream),
+      dev->table.clear();
+      HIP_TRY(hipMemcpyAsync(dev->ptr, tab.data(), table_bytes, hipMemcpyHostToDevice, c.stream),
               "copy channel table");
       HIP_TRY(hipStreamSynchronize(c.stream), "synchronise");
+      dev->table = std::move(tab);
     }
   }
 

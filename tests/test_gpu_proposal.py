@@ -295,6 +295,29 @@ def test_spatial_seven_species_learned_steps(O):
     assert all(np.isfinite(st["E_total"]) for st in stats)
 
 
+def test_learned_cell_blocks_ragged(O):
+    """The learned kernel orders its workgroups in blocks of 32 cells; 45
+    cells (one full block and one of 13, 7 species, 4^3 momenta) against the
+    oracle, every cell and channel once."""
+    _case("learned 45 cells (cell blocks 32 + 13) fp32")
+    wl = W.Workload("qg7_5x3x3_4cube", (5, 3, 3), (4, 4, 4), (6.0, 6.0, 6.0), (2.0, 2.0, 2.0),
+                    0x7F, 16, "f32", 1, 0.01)
+    f = W.random_f(41, wl.cells, wl.nodes) * 0.5
+    g = O.Grid(n_x=wl.n_x, n_p=wl.n_p, x_half=wl.x_half, p_half=wl.p_half, species_mask=wl.species_mask)
+    rows = len(O.channels(g)) * wl.nodes
+    thr, mu, sg = W.random_mog_table(42, rows, K=8, alpha=0.1, mu_scale=1.0, log_sigma=(-1.0, 0.5))
+    with qgbe.Solver(**_kw(wl), precision=qgbe.FP32) as s:
+        s.set_f(f)
+        qgbe.qgbe_set_step_index(s.ctx, 1)
+        qgbe.qgbe_set_proposal_table(s.ctx, thr, mu, sg)
+        A, _, _, _ = s.collision(wl.n_samples, sampler=qgbe.SAMPLER_LEARNED)
+    m = O.masses(g, f)
+    A_ref, S_ref, _ = O.collision_learned(g, f, m, SEED, 1, wl.n_samples, thr, mu, sg)
+    err = np.abs(A - A_ref)
+    assert np.all(err <= 1e-4 * S_ref + 1e-300), float((err / np.maximum(S_ref, 1e-300)).max())
+    assert np.abs(A_ref).max() > 0
+
+
 def test_learned_sixteen_components(O):
     """A host-set table of 16 components: the FP64 learned sampler agrees with
     the oracle; an FP32 context (whose LDS row of component constants holds 8)

@@ -66,6 +66,55 @@ def test_full_size_items_and_conservation(O, wl):
     assert np.count_nonzero(scale) > 100
 
 
+def _neighbourhood_max(S, n_p):
+    """max of S over each node's 3x3x3 momentum neighbourhood (clamped at the box)"""
+    X = S.reshape(S.shape[:2] + tuple(n_p))
+    out = X.copy()
+    for ax in (2, 3, 4):
+        n = X.shape[ax]
+        lo = np.take(out, np.r_[0, np.arange(n - 1)], axis=ax)
+        hi = np.take(out, np.r_[np.arange(1, n), n - 1], axis=ax)
+        out = np.maximum(out, np.maximum(lo, hi))
+    return out.reshape(S.shape)
+
+
+@pytest.mark.parametrize("wl,n", [(W.C2, 256), (W.C3, W.C3.n_samples)], ids=["C2_N256", "C3_N4096"])
+def test_full_size_fp32_term_against_fp64(wl, n):
+    """The whole FP32 collision term at full size, in the launches bench.py
+    times (C2's 512 workgroups do not depend on N; C3 at its own N), against
+    the FP64 kernel on the same samples: a second implementation with global
+    f and global atomic deposits, pinned to the oracle on small grids.
+
+    Bar, element by element: 1e-4 of the FP64 term's scale S at the node, plus
+    2e-5 of the largest S in the node's 3x3x3 momentum neighbourhood.  The
+    second term is the FP32 stencil weights' rounding: a weight w carries an
+    absolute error up to 2^-25, so a corner value v (1 - w) of a deposit is off
+    by up to 3 2^-25 |v| whatever its size; every sample that deposits at a
+    node puts at least |v|/8 on a node of its 2x2x2 stencil, which lies in the
+    neighbourhood, so the error is at most 3 2^-25 * 8 * 27 = 1.9e-5 of the
+    neighbourhood's largest S.  At nodes reached only by corners of weight
+    ~1e-5 (C2: 14 of 1.4e7 elements, values ~1e-10 of the cell's), this term,
+    not the first, bounds the FP32 path."""
+    _case(f"full size {wl.name} fp32 against fp64 N={n}")
+    f = W.initial_f(wl)
+    with _solver(wl) as s:
+        s.set_f(f)
+        qgbe.qgbe_set_step_index(s.ctx, 7)
+        A32 = s.collision(n)[0]
+    with qgbe.Solver(n_x=wl.n_x, n_p=wl.n_p, x_half=wl.x_half, p_half=wl.p_half, species_mask=wl.species_mask,
+                     alpha_s=wl.alpha_s, seed=SEED, precision=qgbe.FP64) as s:
+        s.set_f(f)
+        qgbe.qgbe_set_step_index(s.ctx, 7)
+        A64, S64, _, _ = s.collision(n, scale=True)
+    err = np.abs(A32 - A64)
+    bar = 1e-4 * S64 + 2e-5 * _neighbourhood_max(S64, wl.n_p) + 1e-300
+    assert np.all(err <= bar), float((err / bar).max())
+    # all but a handful of elements meet the first term alone
+    assert np.count_nonzero(err > 1e-4 * S64) <= 1e-5 * err.size
+    # the comparison covers the populated nodes (C2: 3.2e5 of 2.0e6 gluon nodes)
+    assert np.count_nonzero(S64) > wl.cells * wl.nodes // 20
+
+
 def test_full_size_steps_conserve_number():
     """Three steps of the pure-gluon spatial workload as bench.py runs it."""
     _case("full size C2 steps")

@@ -65,6 +65,9 @@ hipError_t launch_collide_f32(const CollideArgs& a, int nslot, bool queue, hipSt
 hipError_t set_collide_lds_limit(size_t lds_max, size_t* budget_plain, size_t* budget_learned, size_t* budget_queue);
 // Waves per workgroup of the FP32 kernel (chunks are multiples of it).
 int collide_f32_waves(bool queue);
+// Consecutive observed nodes a wave of the FP32 kernel takes at a time
+// (chunks must be multiples of it; multiples of the waves are).
+int collide_f32_node_block(bool queue, bool learned);
 hipError_t launch_record(const CollideArgs& a, int n_per_item, long long item_stride, long long n_sel, float* rows,
                          hipStream_t stream);
 

@@ -73,3 +73,51 @@ def test_regulator_removes_forward_pole(O):
     for row in (1, 2, 3, 6, 7):
         v = O.msq(row, 2.0, -1e-14, -2.0 + 1e-14, 0.3, ALPHA)
         assert np.isfinite(v) and abs(v) < 1e6
+
+
+def textbook_regulated(row, s, t, u, mu):
+    """The textbook table with its fractions split into terms over one pole
+    each (or a product of poles), and m_g^2 subtracted from t and u wherever
+    they stand in a denominator: the regulator of Table I, which screens the
+    t- and u-channel exchanges and leaves numerators and s poles alone.  At
+    mu = 0 this is `textbook`; every coefficient is the textbook's."""
+    T, U = t - mu, u - mu
+    if row == 1:
+        return 36 * (4 / 9) * (s * s + u * u) / (T * T)
+    if row == 2:
+        return 36 * ((4 / 9) * ((s * s + u * u) / (T * T) + (s * s + t * t) / (U * U))
+                     - (8 / 27) * s * s / (U * T))
+    if row == 3:
+        return 36 * ((4 / 9) * ((s * s + u * u) / (T * T) + (t * t + u * u) / (s * s))
+                     - (8 / 27) * u * u / (s * T))
+    if row == 4:
+        return 36 * (4 / 9) * (t * t + u * u) / (s * s)
+    if row == 5:   # (t^2 + u^2) / (t u) = t / u + u / t
+        return 36 * ((32 / 27) * (t / U + u / T) - (8 / 3) * (t * t + u * u) / (s * s))
+    if row == 6:   # (s^2 + u^2) / (s u) = s / u + u / s
+        return 96 * (-(4 / 9) * (s / U + u / s) + (u * u + s * s) / (T * T))
+    if row == 7:
+        return 256 * (9 / 2) * (3 - t * u / (s * s) - s * u / (T * T) - s * t / (U * U))
+    raise ValueError(row)
+
+
+@pytest.mark.parametrize("row", range(1, 8))
+def test_regulated_rows_match_textbook_with_screened_poles(O, row):
+    """Every row at m_g^2 > 0, rows 5 and 6 included (a regulator on the wrong
+    pole, or on a numerator, changes the value by O(m_g^2 / t))."""
+    rng = np.random.Generator(np.random.PCG64(100 + row))
+    for s, t, u in zip(*_massless_points(seed=7)):
+        mu = rng.uniform(0.05, 1.5)
+        got = O.msq(row, s, t, u, mu, ALPHA) / G4
+        assert got == pytest.approx(textbook_regulated(row, s, t, u, mu), rel=1e-12)
+
+
+@pytest.mark.parametrize("row", range(1, 8))
+def test_regulator_removes_both_poles(O, row):
+    """With m_g^2 > 0 every row stays finite as t -> 0 and as u -> 0, and
+    approaches the regulated textbook value there."""
+    s, mu, eps = 2.0, 0.3, 1e-14
+    for t, u in ((-eps, -s + eps), (-s + eps, -eps)):
+        v = O.msq(row, s, t, u, mu, ALPHA) / G4
+        assert np.isfinite(v) and abs(v) < 1e6
+        assert v == pytest.approx(textbook_regulated(row, s, t, u, mu), rel=1e-9)

@@ -624,9 +624,9 @@ __device__ __forceinline__ void item_node(Item& it, const CollideArgs& A, const 
   const int iz = p1_lin % G.np[2];
   const int iy = (p1_lin / G.np[2]) % G.np[1];
   const int ix = p1_lin / (G.np[2] * G.np[1]);
-  it.p1[0] = -G.ph[0] + (ix + 0.5) * G.dp[0];
-  it.p1[1] = -G.ph[1] + (iy + 0.5) * G.dp[1];
-  it.p1[2] = -G.ph[2] + (iz + 0.5) * G.dp[2];
+  it.p1[0] = node_coord(G.ph[0], G.dp[0], ix);
+  it.p1[1] = node_coord(G.ph[1], G.dp[1], iy);
+  it.p1[2] = node_coord(G.ph[2], G.dp[2], iz);
   it.E1 = sqrt(it.p1[0] * it.p1[0] + it.p1[1] * it.p1[1] + it.p1[2] * it.p1[2] + it.m1sq);
   it.f1 = A.f64[((size_t)ch.sp[0] * G.cells + it.cell) * G.nodes + p1_lin];
   it.pref = it.coef * G.g4 * kNorm / it.E1;

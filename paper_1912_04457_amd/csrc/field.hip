@@ -15,9 +15,9 @@ __device__ __forceinline__ void node_p(const Grid& G, int node, double p[3]) {
   const int iz = node % G.np[2];
   const int iy = (node / G.np[2]) % G.np[1];
   const int ix = node / (G.np[2] * G.np[1]);
-  p[0] = -G.ph[0] + (ix + 0.5) * G.dp[0];
-  p[1] = -G.ph[1] + (iy + 0.5) * G.dp[1];
-  p[2] = -G.ph[2] + (iz + 0.5) * G.dp[2];
+  p[0] = node_coord(G.ph[0], G.dp[0], ix);
+  p[1] = node_coord(G.ph[1], G.dp[1], iy);
+  p[2] = node_coord(G.ph[2], G.dp[2], iz);
 }
 
 __device__ __forceinline__ double block_sum(double v, double* sh) {

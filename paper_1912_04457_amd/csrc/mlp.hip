@@ -353,8 +353,8 @@ __global__ void features_kernel(Grid G, const Channel* __restrict__ chans, int n
   if (r >= nch * G.nodes) return;
   const int ci = r / G.nodes, node = r % G.nodes;
   const int iz = node % G.np[2], iy = (node / G.np[2]) % G.np[1], ix = node / (G.np[2] * G.np[1]);
-  const double p[3] = {-G.ph[0] + (ix + 0.5) * G.dp[0], -G.ph[1] + (iy + 0.5) * G.dp[1],
-                       -G.ph[2] + (iz + 0.5) * G.dp[2]};
+  const double p[3] = {node_coord(G.ph[0], G.dp[0], ix), node_coord(G.ph[1], G.dp[1], iy),
+                       node_coord(G.ph[2], G.dp[2], iz)};
   const double pn = sqrt(G.ph[0] * G.ph[0] + G.ph[1] * G.ph[1] + G.ph[2] * G.ph[2]);
   const int sp = chans[ci].sp[0];
   const double a = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);

@@ -15,6 +15,17 @@ constexpr double kHbarC = 0.1973269804;  // GeV fm
 // Helicity x colour degeneracy (Eq. C_quark: N_q = 2*3, Eq. C_gluon: N_g = 2*8).
 __host__ __device__ inline double degeneracy(int sp) { return sp == kGluon ? 16.0 : 6.0; }
 
+// Momentum coordinate of node i on an axis of half-width ph and spacing dp:
+// the centre of its momentum cell, -ph + (i + 1/2) dp, with the product
+// rounded before the sum (no fused multiply-add).  The middle node of an odd
+// axis then sits at exactly p = 0 (the fused form leaves ph times the
+// rounding error of dp, about 1e-16), so a massless particle there has E = 0
+// and the node zero measure in the mass integral and the collision term.
+__host__ __device__ inline double node_coord(double ph, double dp, int i) {
+#pragma clang fp contract(off)
+  return -ph + (i + 0.5) * dp;
+}
+
 // One collision channel: a Table I reaction with the observed species at
 // position 1.  Positions 2..4 map onto up to three distinct "slots" (species),
 // which are the f tiles read by the interpolation and the accumulators that

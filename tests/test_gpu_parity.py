@@ -88,6 +88,22 @@ def test_seven_species_ragged(O, precision, symmetric):
     _compare(r["A"], r["A_ref"], r["S_ref"], TOL[precision], "A")
 
 
+@pytest.mark.parametrize("mask", [1 << 6, 0x7F], ids=["gluons", "qg7"])
+def test_partial_node_block_fp32(O, mask):
+    """105 momenta (3 x 5 x 7): the compacting variant (the gluon channel) and
+    the plain ones, where chunks and the last node block end inside a block of
+    4 consecutive nodes."""
+    _case(f"3x5x7 nodes mask={mask:#x} fp32")
+    wl = W.Workload("2cells_3x5x7", (2, 1, 1), (3, 5, 7), (3.0, 3.0, 3.0), (2.0, 2.5, 1.5),
+                    mask, 100, "f32", 1, 0.01)
+    f = W.random_f(24, wl.cells, wl.nodes, species_mask=mask)
+    r = _run_pair(O, wl, f, 100, qgbe.FP32, step=6)
+    _compare(r["A"], r["A_ref"], r["S_ref"], TOL[qgbe.FP32], "A")
+    scale_items = np.abs(r["I_ref"]).max()
+    assert np.allclose(r["I"], r["I_ref"], rtol=TOL[qgbe.FP32], atol=TOL[qgbe.FP32] * scale_items)
+    assert np.all(r["S_ref"][6, :, -1] > 0)   # the bar binds at the last node
+
+
 @pytest.mark.parametrize("precision", [qgbe.FP64, qgbe.FP32])
 def test_conservation(O, precision):
     _case(f"conservation precision={precision}")

@@ -154,6 +154,36 @@ def test_learned_collision_parity(O, precision, tol):
         assert abs(A[:, cell].sum()) <= 1e-13 * S_ref[:, cell].sum()
 
 
+# 3 x 5 x 7 = 105 momenta: in the FP32 kernel's blocks of 4 consecutive nodes
+# per wave, the last block holds one node, and chunks end inside a block
+RAGGED_7 = W.Workload("qg7_2cells_3x5x7", (2, 1, 1), (3, 5, 7), (3.0, 3.0, 3.0), (2.0, 2.5, 1.5),
+                      0x7F, 100, "f64", 1, 0.01)
+
+
+@pytest.mark.parametrize("precision,tol", [(qgbe.FP64, 1e-10), (qgbe.FP32, 1e-4)])
+def test_learned_collision_parity_partial_node_block(O, precision, tol):
+    """The learned term on a node count that is not a multiple of the node
+    block (the direct sums of the last, partial block are still added)."""
+    _case(f"learned collision parity 3x5x7 nodes precision={precision}")
+    wl = RAGGED_7
+    f = W.random_f(36, wl.cells, wl.nodes)
+    g = O.Grid(n_x=wl.n_x, n_p=wl.n_p, x_half=wl.x_half, p_half=wl.p_half, species_mask=wl.species_mask)
+    rows = len(O.channels(g)) * wl.nodes
+    thr, mu, sg = W.random_mog_table(37, rows, K=8, alpha=0.1, mu_scale=1.0, log_sigma=(-1.0, 0.5))
+    with qgbe.Solver(**_kw(wl), precision=precision) as s:
+        s.set_f(f)
+        qgbe.qgbe_set_step_index(s.ctx, 4)
+        qgbe.qgbe_set_proposal_table(s.ctx, thr, mu, sg)
+        A, _, _, _ = s.collision(100, sampler=qgbe.SAMPLER_LEARNED)
+    m = O.masses(g, f)
+    A_ref, S_ref, _ = O.collision_learned(g, f, m, SEED, 4, 100, thr, mu, sg)
+    err = np.abs(A - A_ref)
+    assert np.all(err <= tol * S_ref + 1e-300), float((err / np.maximum(S_ref, 1e-300)).max())
+    assert np.all(S_ref[:, :, -1] > 0)   # the bar binds at the last node of every row
+    for cell in range(wl.cells):
+        assert abs(A[:, cell].sum()) <= 1e-13 * S_ref[:, cell].sum()
+
+
 def test_learned_config3_layout_fp32(O):
     """20^3, 7 species: the learned variant's LDS plan reads some f tiles from
     global memory (node quads) and deposits one slot with global atomics."""

@@ -29,24 +29,26 @@ SEED = 0x5EED2019
 TOL = {qgbe.FP64: 1e-10, qgbe.FP32: 1e-4}
 SPATIAL = W.Workload("qg7_3x4x5_6cube", (3, 4, 5), (6, 6, 6), (3.0, 3.0, 3.0), (2.0, 2.0, 2.0),
                      0x7F, 16, "f64", 3, 0.01)
+# odd on every momentum axis: a node at p = 0 (zero velocity, the mass integral's E = m there)
+SPATIAL_ODD = W.Workload("qg7_3x4x5_5x3x7", (3, 4, 5), (5, 3, 7), (3.0, 3.0, 3.0), (2.0, 2.0, 2.0),
+                         0x7F, 16, "f64", 3, 0.01)
 
 
 def _case(name):
     print(f"\n[gpu case] {name}", flush=True)
 
 
-def spatial_f():
-    wl = SPATIAL
+def spatial_f(wl=SPATIAL):
     return W.cell_varied_f(41, wl.n_x, wl.n_p, wl.p_half, wl.x_half)
 
 
+@pytest.mark.parametrize("wl", [SPATIAL, SPATIAL_ODD], ids=["6cube", "5x3x7"])
 @pytest.mark.parametrize("scheme", ["upwind", "central"])
 @pytest.mark.parametrize("precision", [qgbe.FP64, qgbe.FP32])
-def test_step_parity_spatial(O, scheme, precision):
-    _case(f"spatial 3x4x5 step parity scheme={scheme} precision={precision}")
-    wl = SPATIAL
+def test_step_parity_spatial(O, scheme, precision, wl):
+    _case(f"spatial 3x4x5 {wl.n_p} step parity scheme={scheme} precision={precision}")
     g = O.Grid(n_x=wl.n_x, n_p=wl.n_p, x_half=wl.x_half, p_half=wl.p_half, species_mask=wl.species_mask)
-    f0 = spatial_f()
+    f0 = spatial_f(wl)
     st = O.State(f=f0.copy())
     ref = [O.step(g, st, wl.dt_fm, wl.n_samples, SEED, scheme=scheme) for _ in range(wl.steps)]
     drift = qgbe.DRIFT_UPWIND if scheme == "upwind" else qgbe.DRIFT_CENTRAL

@@ -2,8 +2,9 @@
 subsets (channel tables without gluons, with one quark flavour, a single
 species), the smallest grid the method allows (2 nodes per axis, where every
 stencil spans the whole axis), a single sample per point (one lane of a
-wavefront), for the CM-angle sampler in both precisions and the paper's root
-parameterisation (FP64 in either context).  Bars as in the other parity
+wavefront), massless particles on a grid with a node at p = 0, for the
+CM-angle sampler in both precisions and the paper's root parameterisation
+(FP64 in either context).  Bars as in the other parity
 tests: FP64 1e-10 and FP32 1e-4 of the oracle's scale S, element by element,
 and number conservation per cell."""
 import numpy as np
@@ -98,3 +99,31 @@ def test_frozen_species_stay_fixed_across_steps(precision):
             assert np.all(g2[1] == 0.123)
             assert np.array_equal(np.delete(g2[frozen], frozen.index(1), axis=0),
                                   np.delete(f[frozen], frozen.index(1), axis=0))
+
+
+@pytest.mark.parametrize("precision", [qgbe.FP64, qgbe.FP32])
+@pytest.mark.parametrize("mask", [1 << 6, 0x43], ids=["g", "u_d_g"])
+def test_massless_node_at_origin(O, mask, precision):
+    """Constant zero masses on a grid odd on every axis (3 x 5 x 7): the node
+    at p = 0 has E = 0, so as the observed particle it carries no weight; it
+    still takes the deposits of other samples.  Unregulated poles make the
+    scale S large; the bars are relative to it as everywhere."""
+    _case(f"massless, node at p = 0, mask={mask:#x} precision={precision}")
+    n_x, n_p, p_half = (2, 1, 1), (3, 5, 7), (2.0, 2.5, 1.5)
+    f = W.random_f(57, 2, 105, species_mask=mask) * 0.5
+    g = O.Grid(n_x=n_x, n_p=n_p, x_half=(3.0, 3.0, 3.0), p_half=p_half, species_mask=mask)
+    centre = 52                                  # node (1, 2, 3)
+    assert np.all(g.momenta()[centre] == 0.0)
+    with qgbe.Solver(n_x=n_x, n_p=n_p, x_half=(3.0, 3.0, 3.0), p_half=p_half, species_mask=mask,
+                     alpha_s=g.alpha_s, seed=SEED, precision=precision,
+                     mass_mode=qgbe.MASS_CONSTANT, const_mass2=(0.0,) * 7) as s:
+        s.set_f(f)
+        qgbe.qgbe_set_step_index(s.ctx, 5)
+        A, _, I, _ = s.collision(64, items=True)
+        assert np.all(s.masses() == 0.0)
+    A_ref, S_ref, I_ref = O.collision(g, f, np.zeros((7, 2)), SEED, 5, 64, want_items=True)
+    _check(g, A, A_ref, S_ref, TOL[precision])
+    assert np.all(np.isfinite(A)) and np.all(S_ref[6, :, centre] > 0)
+    # the observed particle at p = 0: no direct sums
+    assert np.all(I.reshape(2, -1, 105)[:, :, centre] == 0.0)
+    assert np.all(I_ref.reshape(2, -1, 105)[:, :, centre] == 0.0)
